@@ -1,0 +1,104 @@
+"""Pins of the FP64 MBIR oracle: least squares, an independent minimiser, restart, resume."""
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+from oracle import mbir, radon
+
+N, NZ, NA, ND = 8, 2, 16, 16
+
+
+def _geometry():
+    ang = np.arange(NA) * np.pi / NA
+    return ang, *mbir.radon_ops(ang, N, ND)
+
+
+def _data(seed=20):
+    rng = np.random.default_rng(seed)
+    x_true = rng.uniform(0, 1, (NZ, N, N))
+    ang, A, At = _geometry()
+    b = A(x_true) + 0.01 * rng.standard_normal((NZ, NA, ND))
+    return ang, A, At, b
+
+
+def test_power_iteration_matches_svd():
+    ang, A, At = _geometry()
+    M = radon.radon_matrix(N, ang, ND)
+    top = np.linalg.svd(M, compute_uv=False)[0] ** 2
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=200, safety=1.0)
+    assert abs(L - top) / top < 1e-8
+
+
+def test_unregularised_iterates_reach_least_squares():
+    ang, A, At, b = _data()
+    M = radon.radon_matrix(N, ang, ND)
+    ref = np.stack([np.linalg.lstsq(M, b[z].ravel(), rcond=None)[0].reshape(N, N) for z in range(NZ)])
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=100)
+    st = mbir.run(b, A, At, (NZ, N, N), None, L, iters=2500)
+    assert np.linalg.norm(st.x - ref) / np.linalg.norm(ref) < 1e-6
+    assert st.restarts > 0
+
+
+def test_regularised_minimum_matches_lbfgs():
+    ang, A, At, b = _data(21)
+    prior = mbir.Prior(p=1.2, sigma=1.0, c=0.05, lam=0.5)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=100) + prior.lipschitz()
+    st = mbir.run(b, A, At, (NZ, N, N), prior, L, iters=2500)
+    phi = lambda v: mbir.objective(v.reshape(NZ, N, N), b, A, prior)            # noqa: E731
+    jac = lambda v: mbir.gradient(v.reshape(NZ, N, N), b, A, At, prior).ravel()  # noqa: E731
+    res = minimize(phi, np.zeros(NZ * N * N), jac=jac, method="L-BFGS-B",
+                   options={"maxiter": 20000, "ftol": 1e-15, "gtol": 1e-12, "maxcor": 30})
+    assert abs(phi(st.x.ravel()) - res.fun) / abs(res.fun) < 1e-6
+    assert np.linalg.norm(st.x.ravel() - res.x) / np.linalg.norm(res.x) < 1e-3
+
+
+def test_objective_decreases_and_gradient_matches_fd():
+    ang, A, At, b = _data(22)
+    prior = mbir.Prior(lam=0.3)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, (NZ, N, N))
+    g = mbir.gradient(x, b, A, At, prior)
+    h = 1e-6
+    for idx in [(0, 1, 2), (1, 7, 0), (0, 4, 4)]:
+        e = np.zeros_like(x)
+        e[idx] = h
+        fd = (mbir.objective(x + e, b, A, prior) - mbir.objective(x - e, b, A, prior)) / (2 * h)
+        assert abs(g[idx] - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_restart_resets_momentum():
+    # when <g, x_{k+1} - x_k> > 0 fires, t_k = 1 so beta = 0: y_{k+1} == x_{k+1} and t_{k+1} = golden ratio
+    ang, A, At, b = _data(23)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=50)
+    st = mbir.State(np.zeros((NZ, N, N)), np.zeros((NZ, N, N)))
+    fired = 0
+    for _ in range(200):
+        prev = st.restarts
+        st = mbir.step(st, b, A, At, None, L)
+        if st.restarts > prev:
+            fired += 1
+            assert np.array_equal(st.y, st.x)
+            assert st.t == 0.5 * (1.0 + np.sqrt(5.0))
+    assert fired >= 1
+
+
+def test_resume_is_bit_exact():
+    ang, A, At, b = _data(24)
+    prior = mbir.Prior(lam=0.2, c=0.01, sigma=1.0)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=30) + prior.lipschitz()
+    full = mbir.run(b, A, At, (NZ, N, N), prior, L, iters=6)
+    half = mbir.run(b, A, At, (NZ, N, N), prior, L, iters=3)
+    saved = mbir.State(half.x.copy(), half.y.copy(), half.t, half.k, half.restarts)
+    for _ in range(3):
+        saved = mbir.step(saved, b, A, At, prior, L)
+    assert np.array_equal(saved.x, full.x) and saved.t == full.t
+
+
+@pytest.mark.parametrize("nonneg", [False, True])
+def test_nonneg_projection(nonneg):
+    ang, A, At, b = _data(25)
+    b = -np.abs(b)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=30)
+    st = mbir.run(b, A, At, (NZ, N, N), None, L, iters=5, nonneg=nonneg)
+    assert (st.x.min() >= 0.0) == nonneg
