@@ -1,0 +1,180 @@
+/*
+ * nufftradon — NUFFT-based Radon projector, its adjoint and a qGGMRF MBIR
+ * step for AMD Instinct MI355X (gfx950).  Plain C ABI.
+ *
+ * The operators follow arXiv 2304.12934 (tomoCAM):
+ *   - the Radon transform of a slice (Sec. 2.1, eq. "radon_transform") is
+ *     computed through the central-slice theorem (eq. "fourier_radon"):
+ *     the 2D spectrum of the slice sampled on polar lines is a type-2
+ *     non-uniform FFT (Sec. 2.2, eqs. "nufft"-"nufft3" in reverse order),
+ *     followed by a 1D inverse transform along every line;
+ *   - the adjoint (Sec. 3, eq. "transpose") is the same chain transposed:
+ *     a 1D transform per line, a type-1 non-uniform FFT (spreading onto the
+ *     oversampled grid, eq. "nufft2") and an inverse 2D FFT with division by
+ *     the kernel transform (eq. "nufft3");
+ *   - the prior is the qGGMRF of Sec. 3 (eqs. "reg2", "reg3") over the 26
+ *     neighbours of every voxel; the MBIR step is one accelerated-gradient
+ *     iteration on the objective of eq. "objfn" with the gradient of
+ *     eq. "gradient".
+ *
+ * Discrete geometry.  A slice is f[iy][ix] (float32, row-major) with pixel
+ * centres x = ix - N/2, y = iy - N/2.  Angle theta_a (float64, radians)
+ * has normal (cos theta, sin theta).  The sinogram is s[a][m] (float32)
+ * with bins t_m = m - N_t/2.  The operator is
+ *     s[a][m] = Re (1/N_t) sum_l Fhat_a(k_l) exp(+2 pi i k_l t_m),
+ *     Fhat_a(k) = sum_{x,y} f(x,y) exp(-2 pi i k (x cos theta_a + y sin theta_a)),
+ * with k_l = (l - N_t/2)/N_t; radon_adj is its exact transpose for real
+ * inner products.  The non-uniform FFT approximates Fhat with a
+ * Kaiser-Bessel kernel of width W on a grid oversampled by sigma = 2.
+ *
+ * Stacks.  A plan describes n_slices slices, each with its own size N,
+ * detector count N_t and angle set, addressed by element offsets into flat
+ * caller buffers: the volume at d_vol + vol_off (N*N floats), the sinogram
+ * at d_sino + sino_off (n_angles*N_t floats), its angles at
+ * angles_host + angle_off.  Offsets may alias between slices only for
+ * angles.
+ *
+ * Ownership.  The caller allocates every device buffer, including the
+ * workspace; the library never allocates or frees device memory.  A plan
+ * owns host tables only.  All device calls are asynchronous on the given
+ * stream and return after enqueueing; a plan is used by one stream at a
+ * time.
+ *
+ * Errors.  Every call returns an nr_status and never aborts.  Arguments are
+ * validated before anything is enqueued.  nr_last_error() gives a
+ * thread-local message for the last failure.  Asynchronous device faults
+ * surface as NR_HIP_ERROR on a later call.
+ */
+#ifndef NUFFTRADON_H
+#define NUFFTRADON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nr_status;
+enum {
+  NR_OK = 0,
+  NR_INVALID_ARG = 1,        /* null pointer, bad size, bad parameter      */
+  NR_UNSUPPORTED_SIZE = 2,   /* FFT length outside the compiled set         */
+  NR_WORKSPACE_TOO_SMALL = 3,
+  NR_HIP_ERROR = 4,          /* a HIP runtime call failed                   */
+  NR_NONFINITE = 5,          /* NaN/Inf detected by a device reduction      */
+  NR_INTERNAL = 6
+};
+
+/* Opaque stream handle: a hipStream_t (NULL = the default stream). */
+typedef void* nr_stream;
+
+typedef struct nr_plan nr_plan;
+
+/* One slice of a stack.  n: slice width N (even, >= 8); n_det: detector
+ * bins N_t (even, >= 8); n_angles >= 1.  Offsets are element offsets. */
+typedef struct {
+  int32_t n, n_det, n_angles;
+  int64_t vol_off, sino_off, angle_off;
+} nr_slice;
+
+/* Non-uniform FFT parameters.  sigma: oversampling (only 2.0 is built);
+ * width: kernel width W in grid cells (6, 7 or 8); beta <= 0 selects the
+ * Kaiser-Bessel shape beta = pi*sqrt((W/sigma)^2 (sigma - 1/2)^2 - 0.8). */
+typedef struct {
+  double sigma;
+  int32_t width;
+  double beta;
+} nr_nufft;
+
+const char* nr_status_str(nr_status s);
+const char* nr_last_error(void);
+const char* nr_version(void);
+
+/* Create a plan for a slice stack (host only, no device work).  Copies the
+ * slice array and every referenced angle.  Sorts the polar points of each
+ * distinct geometry into spreading tiles once.  *out is set on success. */
+nr_status nr_plan_create(const nr_slice* slices, int32_t n_slices, const double* angles_host,
+                         const nr_nufft* params, nr_plan** out);
+
+/* Bytes of device workspace the plan needs (tables + per-slice scratch). */
+nr_status nr_plan_workspace_bytes(const nr_plan* plan, size_t* bytes);
+
+/* Bind caller-owned device workspace (256-byte aligned, at least
+ * nr_plan_workspace_bytes) and upload the plan tables on `stream`.  The
+ * workspace must stay valid until the plan is destroyed or re-bound. */
+nr_status nr_plan_bind(nr_plan* plan, void* d_workspace, size_t bytes, nr_stream stream);
+
+nr_status nr_plan_destroy(nr_plan* plan);
+
+/* Set a tuning parameter of a plan (no effect on results beyond float32
+ * summation order).  Keys: "spread_mode" 0 = LDS-tiled spreading (default),
+ * 1 = one thread per point with global atomics (a slow cross-check). */
+nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
+
+/* s = R f for every slice of the plan (Sec. 2, eq. "fourier_radon" via the
+ * type-2 NUFFT).  d_vol: float32 slices at vol_off; d_sino: float32
+ * sinograms at sino_off, overwritten.  Device pointers. */
+nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream stream);
+
+/* g = R^T y for every slice (Sec. 3, eq. "transpose", the exact transpose
+ * of radon_fwd).  d_sino: float32 input; d_vol: float32 output,
+ * overwritten.  Device pointers. */
+nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream);
+
+/* qGGMRF prior (Sec. 3, eqs. "reg2"/"reg3") on a [nz][n][n] float32 volume:
+ *   H(f) = lambda sum_m sum_{n in N26(m)} w_mn rho((f_m - f_n)/sigma),
+ *   rho(u) = u^2/(c + |u|^(2-p)),
+ * with w_face/w_edge/w_corner the weights of the 6/12/8 neighbours (voxels
+ * outside the volume are dropped).  Adds scale * dH/df into d_grad_accum
+ * (in place) and, when d_value is not NULL, writes H(f) as one float64. */
+typedef struct {
+  float p, sigma, c, lambda;
+  float w_face, w_edge, w_corner;
+} nr_prior;
+
+nr_status qggmrf_grad(const float* d_vol, int32_t nz, int32_t n, const nr_prior* prior,
+                      float scale, float* d_grad_accum, double* d_value, nr_stream stream);
+
+/* One accelerated-gradient iteration with gradient restart (Sec. 3, last
+ * paragraph; objective eq. "objfn" with G = 1/2 ||R f - b||^2):
+ *   g = R^T (R y - b) + grad H(y);  x' = y - inv_L * g (max(x',0) if nonneg)
+ *   restart (t = 1) if <g, x' - x> > 0;  t' = (1 + sqrt(1 + 4 t^2))/2
+ *   y' = x' + ((t - 1)/t') (x' - x);  x_prev <- x;  x <- x'
+ * All slices of the plan must share one N and the volume is the plan's
+ * slices stacked in order (prior couples consecutive slices).  d_b: data,
+ * same layout as radon_fwd's output.  d_x, d_x_prev, d_y, d_grad: float32
+ * volumes (d_grad holds g on return).  The prior uses the plan's slices as
+ * consecutive z planes: slice z must sit at vol_off = z*N*N.  d_state: 8
+ * float64 on the device, {t, last <g, x'-x>, nonfinite flag, restart count,
+ * beta, 3 reserved}; set t = 1 and the rest 0 before the first step.
+ * d_scratch: float32 scratch of the plan's sinogram size (max sino_off +
+ * n_angles*N_t).  Everything stays on the device: no host synchronisation;
+ * read d_state when needed (flag != 0 means a NaN/Inf appeared). */
+typedef struct {
+  float inv_L;
+  int32_t nonneg;
+} nr_mbir;
+
+nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
+                    const float* d_b, float* d_x, float* d_x_prev, float* d_y, float* d_grad,
+                    float* d_scratch, double* d_state, nr_stream stream);
+
+/* Host-only helpers (no device needed), used to test the plan's tables.
+ * nr_kb_eval: for the plan-independent kernel with (width, beta), evaluates
+ * phi(u) (normalised to phi(0)=1) at u[i] with the float64 series, phihat
+ * (its continuous Fourier transform, same normalisation) at xi[i], and the
+ * piecewise-polynomial device approximation of phi at u[i]. */
+nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u, const double* xi,
+                     double* phi, double* phihat, double* phi_poly);
+
+/* Describe how a plan splits work: fills counts for slice `index`:
+ * info[0] = oversampled grid G, info[1] = spreading tiles, info[2] = tile
+ * point entries, info[3] = spreading work items, info[4] = polynomial degree. */
+nr_status nr_plan_info(const nr_plan* plan, int32_t index, int64_t* info, int32_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUFFTRADON_H */

@@ -1,0 +1,20 @@
+"""MI355X-native NUFFT Radon projector, adjoint, qGGMRF prior and MBIR step.
+
+The computation lives in ``libnufftradon.so`` (hand-written HIP for gfx950,
+C ABI in ``include/nufftradon.h``); this package is its Python binding.
+"""
+
+from .radon import (  # noqa: F401
+    MBIR,
+    Plan,
+    Prior,
+    QGGMRFFn,
+    RadonFn,
+    SliceGeometry,
+    kb_eval,
+    power_lipschitz,
+    qggmrf_grad,
+)
+
+__all__ = ["Plan", "SliceGeometry", "Prior", "RadonFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
+           "power_lipschitz", "kb_eval"]

@@ -1,0 +1,93 @@
+"""ctypes binding of libnufftradon.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only loads it and
+declares the C signatures of ``include/nufftradon.h``.  Loading fails loudly
+when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnufftradon.so")
+
+NR_OK = 0
+NR_INVALID_ARG = 1
+NR_UNSUPPORTED_SIZE = 2
+NR_WORKSPACE_TOO_SMALL = 3
+NR_HIP_ERROR = 4
+NR_NONFINITE = 5
+NR_INTERNAL = 6
+
+
+class NrSlice(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("n_det", c_int32), ("n_angles", c_int32),
+                ("vol_off", c_int64), ("sino_off", c_int64), ("angle_off", c_int64)]
+
+
+class NrNufft(ctypes.Structure):
+    _fields_ = [("sigma", c_double), ("width", c_int32), ("beta", c_double)]
+
+
+class NrPrior(ctypes.Structure):
+    _fields_ = [("p", c_float), ("sigma", c_float), ("c", c_float), ("lam", c_float),
+                ("w_face", c_float), ("w_edge", c_float), ("w_corner", c_float)]
+
+
+class NrMbir(ctypes.Structure):
+    _fields_ = [("inv_L", c_float), ("nonneg", c_int32)]
+
+
+class NrError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "nr_status_str": (c_char_p, [c_int32]),
+    "nr_last_error": (c_char_p, []),
+    "nr_version": (c_char_p, []),
+    "nr_plan_create": (c_int32, [POINTER(NrSlice), c_int32, POINTER(c_double), POINTER(NrNufft),
+                                 POINTER(c_void_p)]),
+    "nr_plan_workspace_bytes": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nr_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "nr_plan_destroy": (c_int32, [c_void_p]),
+    "nr_plan_tune": (c_int32, [c_void_p, c_char_p, c_int64]),
+    "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,
+                              c_void_p]),
+    "mbir_step": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
+                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nr_kb_eval": (c_int32, [c_int32, c_double, c_int32, POINTER(c_double), POINTER(c_double),
+                             POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    "nr_plan_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), c_int32]),
+}
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it is missing: there is no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2304_12934_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(status: int, where: str) -> None:
+    if status != NR_OK:
+        msg = lib().nr_last_error().decode(errors="replace")
+        raise NrError(status, where, msg)

@@ -1,0 +1,240 @@
+// Workgroup-cooperative complex FFT in LDS for gfx950 (wave64).
+//
+// Stockham auto-sort (each pass reads with stride L/R and writes with stride
+// Ns, so the result lands in natural order without a bit-reversal pass).  A
+// pass loads every butterfly input of the thread into registers, waits at a
+// barrier, then writes its outputs back over the same LDS buffer, so one
+// L-point buffer is enough.  Radices: 8, 4, 2 for the power-of-two part
+// (as many 8s as possible, the remainder as 4s), then 5 and 3.  Twiddles
+// come from a table of exp(-2 pi i m/L), m < L, computed in float64 on the
+// host and rounded once to float32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace nrk {
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 c_conj(float2 a) { return make_float2(a.x, -a.y); }
+
+// multiply by -i (forward transform) or +i (inverse transform)
+template <bool INV>
+__device__ __forceinline__ float2 mul_i(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time radix plan
+// ---------------------------------------------------------------------------
+
+constexpr int pow2_exponent(int v) {
+  int e = 0;
+  while (v > 1 && (v & 1) == 0) {
+    v >>= 1;
+    ++e;
+  }
+  return e;
+}
+
+constexpr int radix_of(int L, int p) {
+  int r[24] = {};
+  int n = 0;
+  const int e = pow2_exponent(L);
+  const int k = e / 3, rem = e % 3;
+  if (rem == 0) {
+    for (int i = 0; i < k; ++i) r[n++] = 8;
+  } else if (rem == 1) {
+    if (k >= 1) {
+      for (int i = 0; i < k - 1; ++i) r[n++] = 8;
+      r[n++] = 4;
+      r[n++] = 4;
+    } else {
+      r[n++] = 2;
+    }
+  } else {
+    for (int i = 0; i < k; ++i) r[n++] = 8;
+    r[n++] = 4;
+  }
+  int o = L >> e;
+  while (o % 5 == 0) {
+    r[n++] = 5;
+    o /= 5;
+  }
+  while (o % 3 == 0) {
+    r[n++] = 3;
+    o /= 3;
+  }
+  return p < n ? r[p] : 1;
+}
+
+constexpr int num_passes(int L) {
+  int n = 0;
+  while (radix_of(L, n) > 1) ++n;
+  return n;
+}
+
+constexpr int span_before(int L, int p) {
+  int s = 1;
+  for (int i = 0; i < p; ++i) s *= radix_of(L, i);
+  return s;
+}
+
+constexpr bool radix_plan_complete(int L) { return span_before(L, num_passes(L)) == L; }
+
+// ---------------------------------------------------------------------------
+// small DFTs, X_k = sum_n x_n exp(-+2 pi i n k / R)
+// ---------------------------------------------------------------------------
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float2 a = v[0], b = v[1];
+    v[0] = c_add(a, b);
+    v[1] = c_sub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float2 a0 = c_add(v[0], v[2]), a1 = c_sub(v[0], v[2]);
+    const float2 a2 = c_add(v[1], v[3]), a3 = mul_i<INV>(c_sub(v[1], v[3]));
+    v[0] = c_add(a0, a2);
+    v[2] = c_sub(a0, a2);
+    v[1] = c_add(a1, a3);
+    v[3] = c_sub(a1, a3);
+  }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    const float h = 0.70710678118654752440f;
+    // W^1 = (1 -+ i)/sqrt(2), W^2 = -+i, W^3 = W^2 W^1
+    const float2 o1 = INV ? make_float2((o[1].x - o[1].y) * h, (o[1].x + o[1].y) * h)
+                          : make_float2((o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h);
+    const float2 o2 = mul_i<INV>(o[2]);
+    const float2 o3t = INV ? make_float2((o[3].x - o[3].y) * h, (o[3].x + o[3].y) * h)
+                           : make_float2((o[3].x + o[3].y) * h, (o[3].y - o[3].x) * h);
+    const float2 o3 = mul_i<INV>(o3t);
+    v[0] = c_add(e[0], o[0]);
+    v[4] = c_sub(e[0], o[0]);
+    v[1] = c_add(e[1], o1);
+    v[5] = c_sub(e[1], o1);
+    v[2] = c_add(e[2], o2);
+    v[6] = c_sub(e[2], o2);
+    v[3] = c_add(e[3], o3);
+    v[7] = c_sub(e[3], o3);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float s3 = 0.86602540378443864676f;  // sin(2 pi/3)
+    const float2 b = c_add(v[1], v[2]);
+    const float2 t = make_float2(v[0].x - 0.5f * b.x, v[0].y - 0.5f * b.y);
+    const float2 u = mul_i<INV>(c_scale(c_sub(v[1], v[2]), s3));
+    v[0] = c_add(v[0], b);
+    v[1] = c_add(t, u);
+    v[2] = c_sub(t, u);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
+    const float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
+    const float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
+    const float s2 = 0.58778525229247312917f;   // sin(4 pi/5)
+    const float2 b1 = c_add(v[1], v[4]), b2 = c_add(v[2], v[3]);
+    const float2 d1 = c_sub(v[1], v[4]), d2 = c_sub(v[2], v[3]);
+    const float2 t1 = make_float2(v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y);
+    const float2 t2 = make_float2(v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y);
+    const float2 u1 = mul_i<INV>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    const float2 u2 = mul_i<INV>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+    v[0] = c_add(v[0], c_add(b1, b2));
+    v[1] = c_add(t1, u1);
+    v[4] = c_sub(t1, u1);
+    v[2] = c_add(t2, u2);
+    v[3] = c_sub(t2, u2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// one Stockham pass and the whole transform
+// ---------------------------------------------------------------------------
+
+template <int L, int T, int P, bool INV>
+__device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ tw, int tid) {
+  constexpr int R = radix_of(L, P);
+  constexpr int Ns = span_before(L, P);
+  constexpr int NB = L / R;
+  constexpr int PER = (NB + T - 1) / T;
+  float2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = tid + i * T;
+    if (NB % T == 0 || j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = s[j + r * NB];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = tid + i * T;
+    if (NB % T == 0 || j < NB) {
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * (L / (Ns * R))];
+          if (INV) w.y = -w.y;
+          v[i][r] = c_mul(v[i][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[i]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[base + r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int T, bool INV, int P = 0>
+__device__ __forceinline__ void fft_passes(float2* s, const float2* __restrict__ tw, int tid) {
+  if constexpr (P < num_passes(L)) {
+    fft_pass<L, T, P, INV>(s, tw, tid);
+    fft_passes<L, T, INV, P + 1>(s, tw, tid);
+  }
+}
+
+// In-place length-L transform of the LDS buffer s by T threads.  Forward:
+// X_k = sum_n x_n exp(-2 pi i nk/L); inverse: the + sign, unnormalised.
+// The caller must have synchronised after filling s; on return s holds the
+// result and the workgroup has synchronised.
+template <int L, int T, bool INV>
+__device__ __forceinline__ void fft_lds(float2* s, const float2* __restrict__ tw, int tid) {
+  static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
+  fft_passes<L, T, INV>(s, tw, tid);
+}
+
+// threads per transform for a length-L FFT
+constexpr int fft_threads(int L) { return L >= 2048 ? 256 : (L >= 512 ? 128 : 64); }
+
+}  // namespace nrk

@@ -1,0 +1,370 @@
+// Host-side plan construction (pure C++; see plan.hpp).
+//
+// Compiled with floating-point contraction off: the spreading bins below and
+// the device kernels must compute identical grid coordinates from the same
+// float64 tables (one rounded multiply, one rounded subtract, ceil).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+namespace nr {
+
+static const int kFftLengths[] = {16,  32,  64,  128,  256,  512,  1024, 2048, 4096, 8192,
+                                  80,  160, 320, 640,  1280, 2560, 5120};
+
+bool fft_length_supported(int L) {
+  for (int v : kFftLengths)
+    if (v == L) return true;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Kaiser-Bessel kernel
+// ---------------------------------------------------------------------------
+
+// Modified Bessel function of the first kind, order 0: the power series
+// sum_k ((x/2)^2)^k / (k!)^2, summed until the terms stop contributing.
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / (double(k) * double(k));
+    sum += term;
+    if (term < 1e-18 * sum) break;
+  }
+  return sum;
+}
+
+double KaiserBessel::phi(double u) const {
+  const double r = 2.0 * u / W;
+  if (std::fabs(r) > 1.0) return 0.0;
+  return bessel_i0(beta * std::sqrt(1.0 - r * r)) / i0beta;
+}
+
+// Continuous Fourier transform of phi: for the window I0(beta sqrt(1-(x/a)^2))
+// on |x| <= a it is 2a sinh(sqrt(beta^2 - (2 pi a xi)^2)) / sqrt(beta^2 - (2 pi a xi)^2)
+// (sin/sqrt past the cut-off), here with a = W/2 and the 1/I0(beta) normalisation.
+double KaiserBessel::phihat(double xi) const {
+  const double t = M_PI * W * xi;
+  const double d = beta * beta - t * t;
+  double v;
+  if (d > 1e-12) {
+    const double r = std::sqrt(d);
+    v = W * std::sinh(r) / r;
+  } else if (d < -1e-12) {
+    const double r = std::sqrt(-d);
+    v = W * std::sin(r) / r;
+  } else {
+    v = W;
+  }
+  return v / i0beta;
+}
+
+// Chebyshev interpolation of each tap weight w_i(z) = phi(z + (W-1)/2 - i) on
+// z in [-1/2, 1/2] at D+1 Chebyshev points, converted to monomials in z.
+static std::vector<double> fit_tap(const KaiserBessel& kb, int i, int D) {
+  const int n = D + 1;
+  std::vector<double> fk(n), c(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double t = std::cos(M_PI * (k + 0.5) / n);   // t in [-1,1], z = t/2
+    fk[k] = kb.phi(0.5 * t + 0.5 * (kb.W - 1) - i);
+  }
+  for (int m = 0; m < n; ++m) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += fk[k] * std::cos(M_PI * m * (k + 0.5) / n);
+    c[m] = (m == 0 ? 1.0 : 2.0) * s / n;
+  }
+  // Chebyshev series in t -> monomials in t (T_{m+1} = 2 t T_m - T_{m-1}).
+  std::vector<double> Tm1(n, 0.0), Tm(n, 0.0), mono(n, 0.0);
+  Tm1[0] = 1.0;                 // T_0
+  if (n > 1) Tm[1] = 1.0;       // T_1
+  for (int k = 0; k < n; ++k) mono[k] += c[0] * Tm1[k];
+  if (n > 1)
+    for (int k = 0; k < n; ++k) mono[k] += c[1] * Tm[k];
+  for (int m = 2; m < n; ++m) {
+    std::vector<double> Tn(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+      if (k > 0) Tn[k] += 2.0 * Tm[k - 1];
+      Tn[k] -= Tm1[k];
+    }
+    for (int k = 0; k < n; ++k) mono[k] += c[m] * Tn[k];
+    Tm1 = Tm;
+    Tm = Tn;
+  }
+  // t = 2 z: coefficient of z^k is mono[k] * 2^k
+  for (int k = 0; k < n; ++k) mono[k] *= std::ldexp(1.0, k);
+  return mono;
+}
+
+void KaiserBessel::init(int width, double beta_in) {
+  W = width;
+  const double sigma = 2.0;
+  beta = beta_in > 0 ? beta_in
+                     : M_PI * std::sqrt((W / sigma) * (W / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+  i0beta = bessel_i0(beta);
+  // degree W + 2: the fit error then sits at the float32 rounding of the
+  // coefficients (a few 1e-8 of phi(0)) for the default shapes
+  D = W + 2;
+  coef.assign(size_t(W) * (D + 1), 0.0f);
+  for (int i = 0; i < W; ++i) {
+    std::vector<double> m = fit_tap(*this, i, D);
+    for (int k = 0; k <= D; ++k) coef[size_t(i) * (D + 1) + k] = float(m[k]);
+  }
+}
+
+double KaiserBessel::phi_poly(double u) const {
+  // locate the tap of u in the convention of plan.hpp for a point at 0: taps
+  // sit at offsets d = z + (W-1)/2 - i with z in (-1/2, 1/2]
+  const double h = 0.5 * (W - 1);
+  for (int i = 0; i < W; ++i) {
+    const double z = u - h + i;
+    if (z > -0.5 && z <= 0.5) {
+      double acc = coef[size_t(i) * (D + 1) + D];
+      for (int k = D - 1; k >= 0; --k) acc = acc * z + coef[size_t(i) * (D + 1) + k];
+      return acc;
+    }
+  }
+  return 0.0;
+}
+
+double KaiserBessel::max_poly_error() const {
+  double e = 0.0;
+  for (int s = 0; s <= 4000; ++s) {
+    const double u = -0.5 * W + 1e-9 + (W - 2e-9) * s / 4000.0;
+    e = std::max(e, std::fabs(phi_poly(u) - phi(u)));
+  }
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// spreading bins
+// ---------------------------------------------------------------------------
+
+void build_spread_bins(const Plan& plan, Geom& g) {
+  const int W = plan.kb.W;
+  const int na = g.key.n_angles;
+  g.tile_w = std::min(64, g.cols);
+  g.tile_h = std::min(32, g.rows);
+  g.tiles_x = (g.cols + g.tile_w - 1) / g.tile_w;
+  g.tiles_y = (g.rows + g.tile_h - 1) / g.tile_h;
+  const int ntiles = g.tiles_x * g.tiles_y;
+  const double halfW = 0.5 * W;
+  // one-cell margin: a point is listed by every tile within one cell of its
+  // footprint, so a last-bit difference in the device's coordinate cannot drop a tap
+  const int margin = 1;
+  std::vector<int32_t> count(ntiles + 1, 0);
+  auto for_tiles = [&](int a, int j, auto&& fn) {
+    const double ux = double(j) * g.gxy[2 * a];
+    const double uy = double(j) * g.gxy[2 * a + 1];
+    const int g0x = int(std::ceil(ux - halfW));
+    const int g0y = int(std::ceil(uy - halfW));
+    const int r0 = std::max(0, g0x + plan.halo - margin);
+    const int r1 = std::min(g.rows - 1, g0x + plan.halo + W - 1 + margin);
+    const int c0 = std::max(0, g0y + g.G / 2 + plan.colpad - margin);
+    const int c1 = std::min(g.cols - 1, g0y + g.G / 2 + plan.colpad + W - 1 + margin);
+    for (int ty = r0 / g.tile_h; ty <= r1 / g.tile_h; ++ty)
+      for (int tx = c0 / g.tile_w; tx <= c1 / g.tile_w; ++tx) fn(ty * g.tiles_x + tx);
+  };
+  for (int a = 0; a < na; ++a)
+    for (int j = 1; j < g.H; ++j) for_tiles(a, j, [&](int t) { count[t + 1]++; });
+  for (int t = 0; t < ntiles; ++t) count[t + 1] += count[t];
+  g.tile_start = count;
+  g.pts.assign(size_t(count[ntiles]), 0);
+  std::vector<int32_t> fill(count.begin(), count.end() - 1);
+  for (int a = 0; a < na; ++a)
+    for (int j = 1; j < g.H; ++j)
+      for_tiles(a, j, [&](int t) { g.pts[size_t(fill[t]++)] = a * g.H + j; });
+  // work items: at most `chunk` points each; tiles cut into several items
+  // accumulate with atomics into a grid region cleared beforehand
+  const int chunk = 1024;
+  // the k = 0 point of every angle sits at the origin: it is summed over the
+  // angles once and spread by the first item of each tile its footprint touches
+  const int d0 = int(std::ceil(-halfW));
+  const int dr0 = d0 + plan.halo, dr1 = d0 + plan.halo + W - 1;
+  const int dc0 = d0 + g.G / 2 + plan.colpad, dc1 = dc0 + W - 1;
+  g.items.clear();
+  g.zero_tiles.clear();
+  for (int t = 0; t < ntiles; ++t) {
+    const int b = g.tile_start[t], e = g.tile_start[t + 1];
+    const int n_items = std::max(1, (e - b + chunk - 1) / chunk);
+    const int ty = t / g.tiles_x, tx = t % g.tiles_x;
+    const bool has_dc = ty * g.tile_h <= dr1 && (ty + 1) * g.tile_h > dr0 &&
+                        tx * g.tile_w <= dc1 && (tx + 1) * g.tile_w > dc0;
+    if (n_items > 1) g.zero_tiles.push_back(t);
+    for (int k = 0; k < n_items; ++k) {
+      const int ib = b + int((int64_t(e - b) * k) / n_items);
+      const int ie = b + int((int64_t(e - b) * (k + 1)) / n_items);
+      const int flags = (n_items > 1 ? kItemAtomic : 0) | (has_dc && k == 0 ? kItemDC : 0);
+      g.items.push_back({t, ib, ie, flags});
+    }
+  }
+  // heaviest items first so the long ones start early
+  std::stable_sort(g.items.begin(), g.items.end(), [](const SpreadItem& x, const SpreadItem& y) {
+    return (x.end - x.begin) > (y.end - y.begin);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* angles,
+                     const nr_nufft* params, Plan& plan, std::string& err) {
+  if (!slices || n_slices <= 0 || !angles) {
+    err = "slices/angles must be non-null and n_slices > 0";
+    return NR_INVALID_ARG;
+  }
+  double sigma = params ? params->sigma : 2.0;
+  int width = params ? params->width : 7;
+  double beta = params ? params->beta : 0.0;
+  if (sigma == 0.0) sigma = 2.0;
+  if (width == 0) width = 7;
+  if (sigma != 2.0) {
+    err = "only oversampling sigma = 2 is built";
+    return NR_UNSUPPORTED_SIZE;
+  }
+  if (width < 6 || width > 8) {
+    err = "kernel width must be 6, 7 or 8";
+    return NR_UNSUPPORTED_SIZE;
+  }
+  if (!(beta <= 0.0 || (beta > 1.0 && beta < 100.0))) {
+    err = "beta must be <= 0 (default shape) or in (1, 100)";
+    return NR_INVALID_ARG;
+  }
+  plan.sigma = sigma;
+  plan.kb.init(width, beta);
+  if (plan.kb.max_poly_error() > 1e-6) {
+    err = "kernel shape beta gives a polynomial fit error above 1e-6";
+    return NR_UNSUPPORTED_SIZE;
+  }
+  // taps of a point reach ceil(W/2) cells beyond the half-plane's edges
+  plan.halo = (width + 1) / 2;
+  plan.colpad = 4;                 // covers W <= 8 on both ends; keeps rows 64-byte aligned
+  plan.slices.assign(slices, slices + n_slices);
+
+  int64_t max_angle = 0;
+  for (int s = 0; s < n_slices; ++s) {
+    const nr_slice& sl = slices[s];
+    if (sl.n < 8 || (sl.n & 1) || sl.n_det < 8 || (sl.n_det & 1) || sl.n_angles < 1) {
+      err = "slice " + std::to_string(s) + ": need even n >= 8, even n_det >= 8, n_angles >= 1";
+      return NR_INVALID_ARG;
+    }
+    if (sl.vol_off < 0 || sl.sino_off < 0 || sl.angle_off < 0) {
+      err = "slice " + std::to_string(s) + ": negative offset";
+      return NR_INVALID_ARG;
+    }
+    const int G = int(sigma * sl.n);
+    if (!fft_length_supported(G) || !fft_length_supported(sl.n_det)) {
+      err = "slice " + std::to_string(s) + ": FFT length " + std::to_string(G) + " or " +
+            std::to_string(sl.n_det) + " is not built (2^a 16..8192 or 5*2^a 80..5120)";
+      return NR_UNSUPPORTED_SIZE;
+    }
+    max_angle = std::max(max_angle, sl.angle_off + sl.n_angles);
+  }
+  plan.angles.assign(angles, angles + max_angle);
+  for (int64_t i = 0; i < max_angle; ++i)
+    if (!std::isfinite(plan.angles[size_t(i)])) {
+      err = "angle " + std::to_string(i) + " is not finite";
+      return NR_INVALID_ARG;
+    }
+
+  std::map<GeomKey, int> geom_index;
+  plan.slice_geom.resize(n_slices);
+  for (int s = 0; s < n_slices; ++s) {
+    const nr_slice& sl = slices[s];
+    GeomKey key{sl.n, sl.n_det, sl.n_angles, sl.angle_off};
+    auto it = geom_index.find(key);
+    if (it != geom_index.end()) {
+      plan.slice_geom[s] = it->second;
+      continue;
+    }
+    Geom g;
+    g.key = key;
+    g.G = int(sigma * sl.n);
+    g.H = sl.n_det / 2 + 1;
+    g.rows = g.G / 2 + 1 + 2 * plan.halo;
+    g.cols = g.G + 2 * plan.colpad;
+    g.gxy.resize(size_t(2) * sl.n_angles);
+    g.flip.resize(sl.n_angles);
+    for (int a = 0; a < sl.n_angles; ++a) {
+      const double th = plan.angles[size_t(sl.angle_off + a)];
+      double cx = std::cos(th), cy = std::sin(th);
+      // conjugate symmetry of the spectrum of a real slice: points with a
+      // negative first coordinate are read at -u and conjugated
+      const int fl = cx < 0.0 ? 1 : 0;
+      if (fl) {
+        cx = -cx;
+        cy = -cy;
+      }
+      g.gxy[2 * a] = double(g.G) * cx / double(sl.n_det);
+      g.gxy[2 * a + 1] = double(g.G) * cy / double(sl.n_det);
+      g.flip[a] = fl;
+    }
+    build_spread_bins(plan, g);
+    plan.slice_geom[s] = int(plan.geoms.size());
+    geom_index[key] = int(plan.geoms.size());
+    plan.geoms.push_back(std::move(g));
+  }
+
+  // tables: deapodisation per N, twiddles per FFT length
+  for (const Geom& g : plan.geoms) {
+    const int n = g.key.n;
+    if (!plan.deapod.count(n)) {
+      std::vector<float> d(n);
+      for (int i = 0; i < n; ++i) d[i] = float(1.0 / plan.kb.phihat(double(i - n / 2) / g.G));
+      plan.deapod[n] = d;
+    }
+    for (int L : {g.G, g.key.n_det}) {
+      if (plan.twiddle.count(L)) continue;
+      std::vector<f2> tw(L);
+      for (int m = 0; m < L; ++m) {
+        const double ph = -2.0 * M_PI * double(m) / double(L);
+        tw[m] = {float(std::cos(ph)), float(std::sin(ph))};
+      }
+      plan.twiddle[L] = tw;
+    }
+  }
+
+  // workspace layout
+  size_t off = 0;
+  for (auto& kv : plan.deapod) {
+    plan.off_deapod[kv.first] = off;
+    off = align_up(off + kv.second.size() * sizeof(float), 256);
+  }
+  for (auto& kv : plan.twiddle) {
+    plan.off_twiddle[kv.first] = off;
+    off = align_up(off + kv.second.size() * sizeof(f2), 256);
+  }
+  for (Geom& g : plan.geoms) {
+    g.off_gxy = off;
+    off = align_up(off + g.gxy.size() * sizeof(double), 256);
+    g.off_flip = off;
+    off = align_up(off + g.flip.size() * sizeof(int32_t), 256);
+    g.off_pts = off;
+    off = align_up(off + g.pts.size() * sizeof(int32_t), 256);
+    g.off_items = off;
+    off = align_up(off + g.items.size() * sizeof(SpreadItem), 256);
+    g.off_zero = off;
+    off = align_up(off + std::max<size_t>(1, g.zero_tiles.size()) * sizeof(int32_t), 256);
+  }
+  plan.off_slot = off;
+  size_t t_bytes = 0, ext_bytes = 0, yh_bytes = 0;
+  for (const Geom& g : plan.geoms) {
+    t_bytes = std::max(t_bytes, size_t(g.G / 2 + 1) * g.key.n * sizeof(f2));
+    ext_bytes = std::max(ext_bytes, size_t(g.rows) * g.cols * sizeof(f2));
+    yh_bytes = std::max(yh_bytes, size_t(g.key.n_angles) * g.H * sizeof(f2));
+  }
+  plan.slot_t = 0;
+  plan.slot_ext = align_up(t_bytes, 256);
+  plan.slot_yh = align_up(plan.slot_ext + ext_bytes, 256);
+  plan.slot_bytes = align_up(plan.slot_yh + yh_bytes, 256);
+  plan.ws_bytes = plan.off_slot + plan.slot_bytes;
+  return NR_OK;
+}
+
+}  // namespace nr

@@ -1,0 +1,107 @@
+// Host-side plan: geometry validation, Kaiser-Bessel tables, per-angle
+// coordinate tables, spreading bins and the workspace layout.  Pure C++ (no
+// HIP) so it can be built and tested on a host without a GPU.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "layout.hpp"
+#include "nufftradon.h"
+
+namespace nr {
+
+// FFT lengths compiled into the device library: 2^a (16..8192) and 5*2^a (80..5120).
+bool fft_length_supported(int L);
+
+struct f2 {
+  float x, y;
+};
+
+// Kaiser-Bessel kernel phi(u) = I0(beta*sqrt(1-(2u/W)^2)) / I0(beta) on |u| <= W/2
+// (Sec. 2.2: the compact spreading kernel of eq. "nufft2"), its continuous
+// Fourier transform (divided out in eq. "nufft3"), and a piecewise polynomial
+// of the W tap weights for the device.
+struct KaiserBessel {
+  int W = 7;
+  double beta = 0.0;
+  int D = 0;                   // polynomial degree
+  std::vector<float> coef;     // [W][D+1], coefficient of z^k for tap i
+  double i0beta = 1.0;
+
+  void init(int width, double beta_in);   // beta_in <= 0: Beatty shape for sigma = 2
+  double phi(double u) const;              // float64 series
+  double phihat(double xi) const;          // closed form
+  double phi_poly(double u) const;         // device polynomial (evaluated in float64)
+  double max_poly_error() const;
+};
+
+double bessel_i0(double x);
+
+// Tap convention shared by host tables and kernels: for a coordinate u (grid
+// units) the first tap is g0 = ceil(u - W/2); tap i sits at g0 + i with offset
+// d_i = u - g0 - i = z + (W-1)/2 - i, where z = u - g0 - (W-1)/2 lies in (-1/2, 1/2].
+
+struct GeomKey {
+  int n, n_det, n_angles;
+  int64_t angle_off;
+  bool operator<(const GeomKey& o) const {
+    return std::tie(n, n_det, n_angles, angle_off) < std::tie(o.n, o.n_det, o.n_angles, o.angle_off);
+  }
+};
+
+
+struct Geom {
+  GeomKey key;
+  int G = 0;            // oversampled grid size (sigma * N)
+  int H = 0;            // half-line points N_t/2 + 1
+  int rows = 0;         // extended grid rows G/2 + 1 + 2*halo
+  int cols = 0;         // extended grid row length G + 2*colpad
+  std::vector<double> gxy;          // per angle: (G cos/N_t, G sin/N_t), sign-flipped so that x >= 0
+  std::vector<int32_t> flip;        // per angle: 1 if the spectrum value is conjugated
+  // spreading bins (tile-major point lists; points j >= 1 only)
+  int tile_w = 0, tile_h = 0, tiles_x = 0, tiles_y = 0;
+  std::vector<int32_t> pts;         // point ids a*H + j, grouped by tile
+  std::vector<int32_t> tile_start;  // tiles_x*tiles_y + 1 offsets into pts
+  std::vector<SpreadItem> items;
+  std::vector<int32_t> zero_tiles;  // tiles written by atomic items: cleared first
+  // workspace offsets (bytes)
+  size_t off_gxy = 0, off_flip = 0, off_pts = 0, off_items = 0, off_zero = 0;
+};
+
+struct Plan {
+  std::vector<nr_slice> slices;
+  std::vector<int> slice_geom;
+  std::vector<Geom> geoms;
+  std::vector<double> angles;       // copy of every referenced angle (indexed by angle_off + a)
+  KaiserBessel kb;
+  double sigma = 2.0;
+  int halo = 0;                     // (W-1)/2 rounded up: extra grid rows/cols each side
+  int colpad = 0;
+
+  std::map<int, std::vector<float>> deapod;   // N -> 1/phihat((i - N/2)/G)
+  std::map<int, size_t> off_deapod;
+  std::map<int, std::vector<f2>> twiddle;     // L -> exp(-2 pi i m / L)
+  std::map<int, size_t> off_twiddle;
+
+  size_t off_slot = 0;
+  size_t slot_t = 0, slot_ext = 0, slot_yh = 0;   // offsets inside the slot
+  size_t slot_bytes = 0;
+  size_t ws_bytes = 0;
+
+  void* d_ws = nullptr;
+  size_t d_ws_bytes = 0;
+};
+
+// Builds the plan; returns NR_OK or an error status with a message.
+nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* angles,
+                     const nr_nufft* params, Plan& plan, std::string& err);
+
+// Fills the spreading bins of one geometry (called by build_plan).
+void build_spread_bins(const Plan& plan, Geom& g);
+
+}  // namespace nr

@@ -1,0 +1,514 @@
+// HIP kernels of the NUFFT Radon projector (forward chain F1-F4) and its
+// exact transpose (adjoint chain A1-A4) for gfx950.
+//
+// Data layout of one slice in the workspace (complex = float2):
+//   T    [G/2+1][N]            row transform of the slice, stored transposed
+//                              (one contiguous column per kept frequency qx)
+//   ext  [rows][cols]          oversampled half-plane spectrum qx in [0, G/2]
+//                              plus `halo` rows on each side and `colpad`
+//                              columns on each side, so that every 7x7 (WxW)
+//                              kernel footprint is a plain rectangle:
+//                                row r  <-> qx = r - halo
+//                                col p  <-> qy = p - colpad - G/2
+//                              Halo cells hold copies (periodic qy) and
+//                              conjugate mirrors (qx < 0 and qx > G/2, by
+//                              Hermitian symmetry of a real slice).
+//   yh   [n_angles][N_t/2+1]   half-line spectra of the adjoint input
+//
+// Forward (Sec. 2.2, eqs. "nufft"-"nufft3" in reverse order):
+//   F1 k_fwd_rows   divide by phihat(x/G) phihat(y/G), zero-pad to G,
+//                   R2C along x for two rows at once, write T transposed
+//   F2 k_fwd_cols   C2C along y per kept qx, write ext (with halo cells)
+//   F3+F4 k_fwd_interp  per pair of angles: WxW Kaiser-Bessel interpolation
+//                   onto the half-line k_j = j/N_t, then the 1D inverse DFT
+//                   along the line (Hermitian, two angles packed in one
+//                   complex transform), 1/N_t, real sinogram rows
+// Adjoint (Sec. 3, eq. "transpose"): the transpose of every step in reverse:
+//   A1 k_adj_radial  R2C of two sinogram rows, weights c_j/N_t
+//   A2 k_spread_*    WxW spreading onto ext (LDS tiles, or plain atomics)
+//   A3 k_adj_cols    fold halo cells back, inverse C2C along y, keep N rows
+//   A4 k_adj_rows    inverse half-spectrum transform along x for two rows,
+//                    deapodise, real output
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.hpp"
+#include "radon_kernels.hpp"
+
+namespace nrk {
+
+// ---------------------------------------------------------------------------
+// Kaiser-Bessel tap weights
+// ---------------------------------------------------------------------------
+
+// Coordinates of a polar point j on angle table entry (gx, gy): u = j*(gx, gy)
+// in grid cells, first tap g0 = ceil(u - W/2) and the W weights
+// phi(u - g0 - i) from the piecewise polynomial in z = u - g0 - (W-1)/2.
+// The multiply and subtract are rounded separately so the host's spreading
+// bins see the same g0.
+template <int W>
+__device__ __forceinline__ void point_taps(double gx, double gy, int j, const KBArgs& kb, int& g0x,
+                                           int& g0y, float* wx, float* wy) {
+  constexpr int D = W + 2;
+  const double ux = __dmul_rn(double(j), gx);
+  const double uy = __dmul_rn(double(j), gy);
+  const double fx = ceil(__dsub_rn(ux, 0.5 * W));
+  const double fy = ceil(__dsub_rn(uy, 0.5 * W));
+  g0x = int(fx);
+  g0y = int(fy);
+  const float zx = float(ux - fx - 0.5 * (W - 1));
+  const float zy = float(uy - fy - 0.5 * (W - 1));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    float ax = kb.c[i * (D + 1) + D], ay = ax;
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+      ax = fmaf(ax, zx, kb.c[i * (D + 1) + k]);
+      ay = fmaf(ay, zy, kb.c[i * (D + 1) + k]);
+    }
+    wx[i] = ax;
+    wy[i] = ay;
+  }
+}
+
+template <int L>
+__device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
+  return x < 0 ? x + L : (x >= L ? x - L : x);
+}
+
+// ---------------------------------------------------------------------------
+// F1: rows (along x), two at a time, transposed store into T
+// ---------------------------------------------------------------------------
+
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(SliceArgs a) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int N = a.N;
+  const int iy0 = 2 * blockIdx.x;
+  const float* __restrict__ f0 = a.vol_in + size_t(iy0) * N;
+  const float d0 = a.deapod[iy0], d1 = a.deapod[iy0 + 1];
+  // x = ix - N/2 sits at index x mod L
+  for (int n = tid; n < L; n += T) {
+    const int ix = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
+    float2 v = make_float2(0.f, 0.f);
+    if (ix >= 0) {
+      const float dx = a.deapod[ix];
+      v.x = dx * d0 * f0[ix];
+      v.y = dx * d1 * f0[N + ix];
+    }
+    s[n] = v;
+  }
+  __syncthreads();
+  fft_lds<L, T, false>(s, a.tw_G, tid);
+  // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
+  float4* __restrict__ out = reinterpret_cast<float4*>(a.T);
+  for (int q = tid; q <= L / 2; q += T) {
+    const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
+    float4 o;
+    o.x = 0.5f * (z1.x + z2.x);
+    o.y = 0.5f * (z1.y - z2.y);
+    o.z = 0.5f * (z1.y + z2.y);
+    o.w = 0.5f * (z2.x - z1.x);
+    out[(size_t(q) * N + iy0) >> 1] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F2: columns (along y) per kept qx, into the extended grid
+// ---------------------------------------------------------------------------
+
+// store v at natural frequency index n of a grid row (and its periodic copies)
+template <int L>
+__device__ __forceinline__ void store_row(float2* row, int colpad, int n, float2 v) {
+  const int p = wrap_index<L>(n + L / 2) + colpad;
+  row[p] = v;
+  if (p >= L) row[p - L] = v;                            // left pad: qy < -L/2
+  if (p < 2 * colpad) row[p + L] = v;                    // right pad: qy >= L/2
+}
+
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(SliceArgs a) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int N = a.N;
+  const int qx = blockIdx.x;
+  const float2* __restrict__ col = a.T + size_t(qx) * N;
+  for (int n = tid; n < L; n += T) {
+    const int iy = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
+    s[n] = iy >= 0 ? col[iy] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<L, T, false>(s, a.tw_G, tid);
+  const int halo = a.halo, colpad = a.colpad, cols = a.cols;
+  float2* row = a.ext + size_t(qx + halo) * cols;
+  // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
+  float2* m1 = (qx >= 1 && qx <= halo) ? a.ext + size_t(halo - qx) * cols : nullptr;
+  float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? a.ext + size_t(L - qx + halo) * cols : nullptr;
+  for (int n = tid; n < L; n += T) {
+    const float2 v = s[n];
+    store_row<L>(row, colpad, n, v);
+    const int nm = n == 0 ? 0 : L - n;
+    if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
+    if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F3 + F4: interpolation onto two half-lines and the radial inverse DFT
+// ---------------------------------------------------------------------------
+
+template <int W>
+__device__ __forceinline__ float2 interp_point(const SliceArgs& a, const KBArgs& kb, int ang, int j) {
+  int g0x, g0y;
+  float wx[W], wy[W];
+  point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+  const float2* __restrict__ p = a.ext + size_t(g0x + a.halo) * a.cols + (g0y + a.G / 2 + a.colpad);
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int l = 0; l < W; ++l) {
+      const float2 v = p[l];
+      r.x = fmaf(wy[l], v.x, r.x);
+      r.y = fmaf(wy[l], v.y, r.y);
+    }
+    acc.x = fmaf(wx[i], r.x, acc.x);
+    acc.y = fmaf(wx[i], r.y, acc.y);
+    p += a.cols;
+  }
+  if (a.flip[ang]) acc.y = -acc.y;
+  return acc;
+}
+
+template <int L, int W>
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBArgs kb) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
+  const bool has1 = a1 < a.na;
+  const float inv = 1.0f / float(L);
+  // pack the Hermitian completions of both half-lines: Z = X + iY
+  for (int j = tid; j <= L / 2; j += T) {
+    float2 X = c_scale(interp_point<W>(a, kb, a0, j), inv);
+    float2 Y = has1 ? c_scale(interp_point<W>(a, kb, a1, j), inv) : make_float2(0.f, 0.f);
+    if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
+      X.y = 0.f;
+      Y.y = 0.f;
+    }
+    s[j] = make_float2(X.x - Y.y, X.y + Y.x);
+    if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
+  }
+  __syncthreads();
+  fft_lds<L, T, true>(s, a.tw_Nt, tid);
+  // bin m (t = m - N_t/2) is output index t mod N_t
+  float* __restrict__ o0 = a.sino_out + size_t(a0) * L;
+  for (int m = tid; m < L; m += T) {
+    const float2 z = s[wrap_index<L>(m + L / 2)];
+    o0[m] = z.x;
+    if (has1) o0[L + m] = z.y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A1: radial transform of two sinogram rows
+// ---------------------------------------------------------------------------
+
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(SliceArgs a) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
+  const bool has1 = a1 < a.na;
+  const float* __restrict__ y0 = a.sino_in + size_t(a0) * L;
+  for (int m = tid; m < L; m += T)
+    s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? y0[L + m] : 0.f);
+  __syncthreads();
+  fft_lds<L, T, false>(s, a.tw_Nt, tid);
+  const int H = L / 2 + 1;
+  float2* __restrict__ o0 = a.yh + size_t(a0) * H;
+  const float inv = 1.0f / float(L);
+  for (int j = tid; j < H; j += T) {
+    const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
+    const float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
+    o0[j] = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
+    if (has1) o0[H + j] = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A2: spreading (type-1 gridding) onto the extended grid
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_zero(float4* p, size_t n4) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// clear the tiles that several work items accumulate into
+__global__ __launch_bounds__(256) void k_spread_zero(SliceArgs a) {
+  const int t = a.zero_tiles[blockIdx.x];
+  const int r0 = (t / a.tiles_x) * a.tile_h, c0 = (t % a.tiles_x) * a.tile_w;
+  for (int c = threadIdx.x; c < a.tile_w * a.tile_h; c += blockDim.x) {
+    const int r = r0 + c / a.tile_w, cc = c0 + c % a.tile_w;
+    if (r < a.rows && cc < a.cols) a.ext[size_t(r) * a.cols + cc] = make_float2(0.f, 0.f);
+  }
+}
+
+// One work item = one grid tile (TH rows x TW columns) and a range of the
+// points whose footprint touches it.  The tile accumulates in LDS with LDS
+// float atomics; single-item tiles are then stored plainly (covering every
+// cell, zeros included), shared tiles are added with global atomics.
+template <int W, int TW, int TH>
+__global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
+  __shared__ float acc_re[TH * TW];
+  __shared__ float acc_im[TH * TW];
+  __shared__ float red[256];
+  const SpreadItem it = a.items[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < TH * TW; c += 256) {
+    acc_re[c] = 0.f;
+    acc_im[c] = 0.f;
+  }
+  const int r0 = (it.tile / a.tiles_x) * TH, c0 = (it.tile % a.tiles_x) * TW;
+  const int rbase = a.halo - r0, cbase = a.G / 2 + a.colpad - c0;
+  __syncthreads();
+  if (it.flags & 2) {
+    // k = 0 of every angle sits at the origin: sum them, spread once
+    float sum = 0.f;
+    for (int ang = tid; ang < a.na; ang += 256) sum += a.yh[size_t(ang) * a.H].x;
+    red[tid] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid < W * W) {
+      int g0x, g0y;
+      float wx[W], wy[W];
+      point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
+      const int i = tid / W, l = tid % W;
+      const int rr = g0x + i + rbase, cc = g0y + l + cbase;
+      if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) atomicAdd(&acc_re[rr * TW + cc], red[0] * wx[i] * wy[l]);
+    }
+  }
+  for (int e = it.begin + tid; e < it.end; e += 256) {
+    const int pid = a.pts[e];
+    const int ang = pid / a.H, j = pid - ang * a.H;
+    float2 v = a.yh[pid];
+    if (a.flip[ang]) v.y = -v.y;
+    int g0x, g0y;
+    float wx[W], wy[W];
+    point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+    const int rr0 = g0x + rbase, cc0 = g0y + cbase;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const int rr = rr0 + i;
+      if (rr < 0 || rr >= TH) continue;
+      const float vx = wx[i] * v.x, vy = wx[i] * v.y;
+#pragma unroll
+      for (int l = 0; l < W; ++l) {
+        const int cc = cc0 + l;
+        if (cc < 0 || cc >= TW) continue;
+        atomicAdd(&acc_re[rr * TW + cc], vx * wy[l]);
+        atomicAdd(&acc_im[rr * TW + cc], vy * wy[l]);
+      }
+    }
+  }
+  __syncthreads();
+  const bool shared_tile = it.flags & 1;
+  for (int c = tid; c < TH * TW; c += 256) {
+    const int r = r0 + c / TW, cc = c0 + c % TW;
+    if (r >= a.rows || cc >= a.cols) continue;
+    float2* dst = a.ext + size_t(r) * a.cols + cc;
+    if (shared_tile) {
+      atomicAdd(&dst->x, acc_re[c]);
+      atomicAdd(&dst->y, acc_im[c]);
+    } else {
+      *dst = make_float2(acc_re[c], acc_im[c]);
+    }
+  }
+}
+
+// Reference spreading: one thread per polar point, global float atomics
+// straight into the (cleared) extended grid.  Slow; used to cross-check.
+template <int W>
+__global__ __launch_bounds__(256) void k_spread_atomic(SliceArgs a, KBArgs kb) {
+  const int pid = blockIdx.x * 256 + threadIdx.x;
+  if (pid >= a.na * a.H) return;
+  const int ang = pid / a.H, j = pid - ang * a.H;
+  float2 v = a.yh[pid];
+  if (a.flip[ang]) v.y = -v.y;
+  int g0x, g0y;
+  float wx[W], wy[W];
+  point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+  float2* p = a.ext + size_t(g0x + a.halo) * a.cols + (g0y + a.G / 2 + a.colpad);
+  for (int i = 0; i < W; ++i)
+    for (int l = 0; l < W; ++l) {
+      atomicAdd(&p[size_t(i) * a.cols + l].x, wx[i] * wy[l] * v.x);
+      atomicAdd(&p[size_t(i) * a.cols + l].y, wx[i] * wy[l] * v.y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A3: fold the halo cells, inverse transform along y, keep N rows
+// ---------------------------------------------------------------------------
+
+// sum of a main cell and its periodic copy in the padded columns
+template <int L>
+__device__ __forceinline__ float2 load_folded(const float2* row, int colpad, int n) {
+  const int p = wrap_index<L>(n + L / 2) + colpad;
+  float2 v = row[p];
+  if (p >= L) v = c_add(v, row[p - L]);
+  if (p < 2 * colpad) v = c_add(v, row[p + L]);
+  return v;
+}
+
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(SliceArgs a) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int qx = blockIdx.x;
+  const int halo = a.halo, colpad = a.colpad, cols = a.cols, N = a.N;
+  const float2* row = a.ext + size_t(qx + halo) * cols;
+  const float2* m1 = (qx >= 1 && qx <= halo) ? a.ext + size_t(halo - qx) * cols : nullptr;
+  const float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? a.ext + size_t(L - qx + halo) * cols : nullptr;
+  for (int n = tid; n < L; n += T) {
+    float2 v = load_folded<L>(row, colpad, n);
+    const int nm = n == 0 ? 0 : L - n;
+    if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+    if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+    s[n] = v;
+  }
+  __syncthreads();
+  fft_lds<L, T, true>(s, a.tw_G, tid);
+  float2* __restrict__ out = a.T + size_t(qx) * N;
+  for (int iy = tid; iy < N; iy += T) out[iy] = s[wrap_index<L>(iy - N / 2)];
+}
+
+// ---------------------------------------------------------------------------
+// A4: transpose of the row R2C: a'(x) = Re sum_{q=0}^{G/2} T'[q] e^{2 pi i q x/G}
+// ---------------------------------------------------------------------------
+
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
+  constexpr int T = fft_threads(L);
+  __shared__ float2 s[L];
+  const int tid = threadIdx.x;
+  const int N = a.N;
+  const int iy0 = 2 * blockIdx.x;
+  const float4* __restrict__ in = reinterpret_cast<const float4*>(a.T);
+  // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
+  for (int q = tid; q <= L / 2; q += T) {
+    const float4 t = in[(size_t(q) * N + iy0) >> 1];
+    float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
+    if (q == 0 || q == L / 2) {
+      X = make_float2(2.f * X.x, 0.f);
+      Y = make_float2(2.f * Y.x, 0.f);
+    }
+    s[q] = make_float2(X.x - Y.y, X.y + Y.x);
+    if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
+  }
+  __syncthreads();
+  fft_lds<L, T, true>(s, a.tw_G, tid);
+  const float d0 = 0.5f * a.deapod[iy0], d1 = 0.5f * a.deapod[iy0 + 1];
+  float* __restrict__ g0 = a.vol_out + size_t(iy0) * N;
+  for (int ix = tid; ix < N; ix += T) {
+    const float2 z = s[wrap_index<L>(ix - N / 2)];
+    const float dx = a.deapod[ix];
+    g0[ix] = dx * d0 * z.x;
+    g0[N + ix] = dx * d1 * z.y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+#define NR_LENGTHS(X) \
+  X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(80) X(160) X(320) X(640) X(1280) X(2560) X(5120)
+
+hipError_t launch_fwd(const SliceArgs& a, const KBArgs& kb, int W, hipStream_t st) {
+  const int G = a.G, Nt = a.Nt;
+  hipError_t e = hipSuccess;
+  switch (G) {
+#define NR_CASE(l)                                                                          \
+  case l:                                                                                   \
+    hipLaunchKernelGGL(k_fwd_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a);        \
+    hipLaunchKernelGGL(k_fwd_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a);      \
+    break;
+    NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nb = (a.na + 1) / 2;
+  switch (Nt) {
+#define NR_CASE(l)                                                                                  \
+  case l:                                                                                           \
+    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
+    if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
+    if (W == 8) hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
+    break;
+    NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj(const SliceArgs& a, const KBArgs& kb, int W, int spread_mode, hipStream_t st) {
+  const int G = a.G, Nt = a.Nt;
+  const int nb = (a.na + 1) / 2;
+  switch (Nt) {
+#define NR_CASE(l)                                                                 \
+  case l:                                                                          \
+    hipLaunchKernelGGL(k_adj_radial<l>, dim3(nb), dim3(fft_threads(l)), 0, st, a); \
+    break;
+    NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (spread_mode == 1) {
+    const size_t n4 = size_t(a.rows) * a.cols / 2;
+    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(a.ext), n4);
+    const int np = a.na * a.H;
+    const dim3 g((np + 255) / 256);
+    if (W == 6) hipLaunchKernelGGL(k_spread_atomic<6>, g, dim3(256), 0, st, a, kb);
+    if (W == 7) hipLaunchKernelGGL(k_spread_atomic<7>, g, dim3(256), 0, st, a, kb);
+    if (W == 8) hipLaunchKernelGGL(k_spread_atomic<8>, g, dim3(256), 0, st, a, kb);
+  } else {
+    if (a.tile_w != 64 || a.tile_h != 32) return hipErrorInvalidValue;
+    if (a.n_zero > 0) hipLaunchKernelGGL(k_spread_zero, dim3(a.n_zero), dim3(256), 0, st, a);
+    if (W == 6) hipLaunchKernelGGL((k_spread_tiles<6, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+    if (W == 7) hipLaunchKernelGGL((k_spread_tiles<7, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+    if (W == 8) hipLaunchKernelGGL((k_spread_tiles<8, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  switch (G) {
+#define NR_CASE(l)                                                                     \
+  case l:                                                                              \
+    hipLaunchKernelGGL(k_adj_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); \
+    hipLaunchKernelGGL(k_adj_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a);   \
+    break;
+    NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nrk

@@ -1,0 +1,314 @@
+"""Python front end: plans, operators, autograd functions and the MBIR driver.
+
+Thin wrappers over libnufftradon: tensors are validated and their device
+pointers handed to the C ABI together with the current HIP stream.  No
+arithmetic of the method runs here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NrMbir, NrNufft, NrPrior, NrSlice, check, lib
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t: torch.Tensor, numel: int, device: torch.device, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, plan is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
+@dataclass
+class SliceGeometry:
+    """One slice of a stack: width ``n``, detector bins ``n_det``, angles (radians)."""
+    n: int
+    n_det: int
+    angles: np.ndarray
+
+
+class Plan:
+    """NUFFT Radon plan for a slice stack, bound to device workspace.
+
+    ``Plan.uniform(n, n_det, angles, n_slices)`` describes ``n_slices`` slices
+    sharing one geometry, with volume ``[Z, n, n]`` and sinogram
+    ``[Z, n_angles, n_det]``.  ``Plan(geoms)`` describes an uneven stack whose
+    volumes and sinograms are packed back to back in flat buffers.
+    """
+
+    def __init__(self, geoms: Sequence[SliceGeometry], width: int = 7, beta: float = 0.0,
+                 device: torch.device | str | None = None, share_angles: bool = True):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self.device.type != "cuda":
+            raise ValueError("the projector runs on a GPU device only")
+        self.geoms = list(geoms)
+        slices = (NrSlice * len(self.geoms))()
+        angle_chunks: list[np.ndarray] = []
+        angle_index: dict[bytes, int] = {}
+        vol_off = sino_off = angle_off = 0
+        self.vol_offsets, self.sino_offsets = [], []
+        for i, g in enumerate(self.geoms):
+            ang = np.ascontiguousarray(np.asarray(g.angles, dtype=np.float64))
+            key = ang.tobytes()
+            if share_angles and key in angle_index:
+                a_off = angle_index[key]
+            else:
+                a_off = angle_off
+                angle_index[key] = a_off
+                angle_chunks.append(ang)
+                angle_off += len(ang)
+            slices[i] = NrSlice(int(g.n), int(g.n_det), len(ang), vol_off, sino_off, a_off)
+            self.vol_offsets.append(vol_off)
+            self.sino_offsets.append(sino_off)
+            vol_off += int(g.n) * int(g.n)
+            sino_off += len(ang) * int(g.n_det)
+        self.vol_numel, self.sino_numel = vol_off, sino_off
+        self._angles = np.ascontiguousarray(np.concatenate(angle_chunks)) if angle_chunks else np.zeros(1)
+        params = NrNufft(2.0, int(width), float(beta))
+        handle = ctypes.c_void_p()
+        L = lib()
+        check(L.nr_plan_create(slices, len(self.geoms),
+                               self._angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(params), ctypes.byref(handle)), "nr_plan_create")
+        self._h = handle
+        nbytes = ctypes.c_size_t()
+        check(L.nr_plan_workspace_bytes(self._h, ctypes.byref(nbytes)), "nr_plan_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        ws_ptr = ctypes.c_void_p(self._ws.data_ptr() + off)
+        with torch.cuda.device(self.device):
+            check(L.nr_plan_bind(self._h, ws_ptr, self.workspace_bytes, _stream(self.device)), "nr_plan_bind")
+        u = self.geoms[0]
+        self.uniform = all(g.n == u.n and g.n_det == u.n_det and len(g.angles) == len(u.angles)
+                           for g in self.geoms)
+
+    @classmethod
+    def uniform_stack(cls, n: int, n_det: int, angles, n_slices: int = 1, **kw) -> "Plan":
+        ang = np.asarray(angles, dtype=np.float64)
+        return cls([SliceGeometry(n, n_det, ang) for _ in range(n_slices)], **kw)
+
+    # --------------------------------------------------------------- shapes
+    @property
+    def n_slices(self) -> int:
+        return len(self.geoms)
+
+    def vol_shape(self):
+        g = self.geoms[0]
+        return (self.n_slices, g.n, g.n) if self.uniform else (self.vol_numel,)
+
+    def sino_shape(self):
+        g = self.geoms[0]
+        return (self.n_slices, len(g.angles), g.n_det) if self.uniform else (self.sino_numel,)
+
+    # ------------------------------------------------------------ operators
+    def fwd(self, vol: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Sinograms ``R f`` of every slice (float32)."""
+        _require(vol, self.vol_numel, self.device, "vol")
+        if out is None:
+            out = torch.empty(self.sino_shape(), dtype=torch.float32, device=self.device)
+        _require(out, self.sino_numel, self.device, "out")
+        with torch.cuda.device(self.device):
+            check(lib().radon_fwd(self._h, _ptr(vol), _ptr(out), _stream(self.device)), "radon_fwd")
+        return out
+
+    def adj(self, sino: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Back-projections ``R^T y`` of every slice (float32)."""
+        _require(sino, self.sino_numel, self.device, "sino")
+        if out is None:
+            out = torch.empty(self.vol_shape(), dtype=torch.float32, device=self.device)
+        _require(out, self.vol_numel, self.device, "out")
+        with torch.cuda.device(self.device):
+            check(lib().radon_adj(self._h, _ptr(sino), _ptr(out), _stream(self.device)), "radon_adj")
+        return out
+
+    def tune(self, key: str, value: int) -> None:
+        check(lib().nr_plan_tune(self._h, key.encode(), int(value)), "nr_plan_tune")
+
+    def info(self, index: int = 0) -> dict:
+        buf = (ctypes.c_int64 * 5)()
+        check(lib().nr_plan_info(self._h, index, buf, 5), "nr_plan_info")
+        return {"G": buf[0], "tiles": buf[1], "tile_entries": buf[2], "spread_items": buf[3], "poly_degree": buf[4]}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().nr_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+# --------------------------------------------------------------------------
+# prior
+# --------------------------------------------------------------------------
+
+def _inverse_distance_weights():
+    total = 6.0 + 12.0 / math.sqrt(2.0) + 8.0 / math.sqrt(3.0)
+    return 1.0 / total, (1.0 / math.sqrt(2.0)) / total, (1.0 / math.sqrt(3.0)) / total
+
+
+@dataclass
+class Prior:
+    """qGGMRF hyper-parameters (defaults: the paper's p = 1.2, sigma = 1/0.7, c = 1e-4)."""
+    p: float = 1.2
+    sigma: float = 1.0 / 0.7
+    c: float = 1e-4
+    lam: float = 1.0
+    weights: tuple = field(default_factory=_inverse_distance_weights)
+
+    def as_c(self) -> NrPrior:
+        wf, we, wc = self.weights
+        return NrPrior(self.p, self.sigma, self.c, self.lam, wf, we, wc)
+
+    def lipschitz(self) -> float:
+        return 8.0 * self.lam / (self.c * self.sigma ** 2)
+
+
+def qggmrf_grad(vol: torch.Tensor, prior: Prior, scale: float = 1.0, grad: torch.Tensor | None = None,
+                value: bool = False):
+    """``grad += scale * dH/dvol`` for a ``[Z, N, N]`` volume; returns ``(grad, H or None)``."""
+    if vol.dim() != 3 or vol.shape[1] != vol.shape[2]:
+        raise ValueError("vol must be [Z, N, N]")
+    _require(vol, vol.numel(), vol.device, "vol")
+    if grad is None:
+        grad = torch.zeros_like(vol)
+    _require(grad, vol.numel(), vol.device, "grad")
+    val = torch.zeros(1, dtype=torch.float64, device=vol.device) if value else None
+    pr = prior.as_c()
+    with torch.cuda.device(vol.device):
+        check(lib().qggmrf_grad(_ptr(vol), vol.shape[0], vol.shape[1], ctypes.byref(pr), float(scale),
+                                _ptr(grad), _ptr(val) if value else None, _stream(vol.device)), "qggmrf_grad")
+    return grad, (val if value else None)
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+class RadonFn(torch.autograd.Function):
+    """``s = R x`` whose backward is the hand-written adjoint ``R^T g``."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, plan: Plan) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.fwd(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.adj(g.contiguous()), None
+
+
+class QGGMRFFn(torch.autograd.Function):
+    """``H(x)`` (float64 scalar) whose backward is the hand-written prior gradient."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, prior: Prior) -> torch.Tensor:
+        grad, val = qggmrf_grad(x.contiguous(), prior, 1.0, None, value=True)
+        ctx.save_for_backward(grad)
+        return val[0]
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (grad,) = ctx.saved_tensors
+        return grad * g.to(grad.dtype), None
+
+
+# --------------------------------------------------------------------------
+# MBIR driver
+# --------------------------------------------------------------------------
+
+class MBIR:
+    """Accelerated-gradient MBIR on the device: one ``mbir_step`` per iteration.
+
+    State ``{x, x_prev, y, grad, t}`` lives on the device; ``step()``
+    enqueues one iteration without synchronising the host.
+    """
+
+    def __init__(self, plan: Plan, b: torch.Tensor, prior: Prior, L: float, nonneg: bool = False,
+                 x0: torch.Tensor | None = None):
+        if not plan.uniform:
+            raise ValueError("MBIR needs a uniform stack (one N for every slice)")
+        self.plan, self.b, self.prior = plan, b.contiguous(), prior
+        _require(self.b, plan.sino_numel, plan.device, "b")
+        shape = plan.vol_shape()
+        dev = plan.device
+        self.x = torch.zeros(shape, dtype=torch.float32, device=dev) if x0 is None else x0.clone().contiguous()
+        self.y = self.x.clone()
+        self.x_prev = self.x.clone()
+        self.grad = torch.zeros_like(self.x)
+        self.scratch = torch.empty(plan.sino_shape(), dtype=torch.float32, device=dev)
+        self.state = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.state[0] = 1.0
+        self.params = NrMbir(1.0 / float(L), 1 if nonneg else 0)
+        self._prior_c = prior.as_c()
+        self.k = 0
+
+    def step(self) -> None:
+        with torch.cuda.device(self.plan.device):
+            check(lib().mbir_step(self.plan._h, ctypes.byref(self._prior_c), ctypes.byref(self.params),
+                                  _ptr(self.b), _ptr(self.x), _ptr(self.x_prev), _ptr(self.y), _ptr(self.grad),
+                                  _ptr(self.scratch), _ptr(self.state), _stream(self.plan.device)), "mbir_step")
+        self.k += 1
+
+    def run(self, iters: int) -> torch.Tensor:
+        for _ in range(iters):
+            self.step()
+        return self.x
+
+    @property
+    def restarts(self) -> int:
+        return int(self.state[3].item())
+
+    @property
+    def nonfinite(self) -> bool:
+        return bool(self.state[2].item() != 0.0)
+
+
+def power_lipschitz(plan: Plan, iters: int = 30, seed: int = 0, safety: float = 1.01) -> float:
+    """Largest eigenvalue of ``R^T R`` for the plan (power iteration, times ``safety``)."""
+    gen = torch.Generator(device=plan.device).manual_seed(seed)
+    v = torch.randn(plan.vol_shape(), generator=gen, device=plan.device, dtype=torch.float32)
+    v /= torch.linalg.vector_norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = plan.adj(plan.fwd(v))
+        lam = float(torch.linalg.vector_norm(w.double()))
+        v = (w / lam).contiguous()
+    return safety * lam
+
+
+def kb_eval(width: int, beta: float, u: np.ndarray, xi: np.ndarray):
+    """Host evaluation of the plan's Kaiser-Bessel tables: (phi(u), phihat(xi), polynomial phi(u))."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = max(len(u), len(xi))
+    phi, ph, poly = np.zeros(n), np.zeros(n), np.zeros(n)
+    P = ctypes.POINTER(ctypes.c_double)
+    uu = np.resize(u, n) if len(u) else np.zeros(n)
+    xx = np.resize(xi, n) if len(xi) else np.zeros(n)
+    check(lib().nr_kb_eval(width, beta, n, uu.ctypes.data_as(P), xx.ctypes.data_as(P), phi.ctypes.data_as(P),
+                           ph.ctypes.data_as(P), poly.ctypes.data_as(P)), "nr_kb_eval")
+    return phi[:len(u)], ph[:len(xi)], poly[:len(u)]

@@ -1,0 +1,117 @@
+"""Host-only checks of libnufftradon (no GPU): exports, Kaiser-Bessel tables, plan validation."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nufftradon.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2304_12934_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:nr_status|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("radon_fwd", "radon_adj", "mbir_step", "qggmrf_grad", "nr_plan_create", "nr_plan_bind"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    from paper_2304_12934_amd import _lib
+    assert set(declared_functions()) <= set(_lib.SIGNATURES)
+
+
+# P7 — Kaiser-Bessel kernel and its Fourier transform
+@pytest.mark.parametrize("W", [6, 7, 8])
+def test_kaiser_bessel_tables(L, W):
+    from paper_2304_12934_amd import kb_eval
+    beta = np.pi * np.sqrt((W / 2.0) ** 2 * 1.5 ** 2 - 0.8)
+    u = np.linspace(-W / 2 + 1e-6, W / 2 - 1e-6, 501)
+    xi = np.linspace(0.0, 0.25, 26)
+    phi, phihat, poly = kb_eval(W, 0.0, u, xi)
+    ref = special.i0(beta * np.sqrt(1 - (2 * u / W) ** 2)) / special.i0(beta)
+    assert np.abs(phi - ref).max() < 1e-13
+    # continuous Fourier transform by quadrature of the kernel itself
+    f = lambda x: special.i0(beta * np.sqrt(max(0.0, 1 - (2 * x / W) ** 2))) / special.i0(beta)  # noqa: E731
+    quad = np.array([integrate.quad(lambda x: f(x) * np.cos(2 * np.pi * k * x), -W / 2, W / 2,
+                                    epsabs=1e-14, epsrel=1e-13, limit=200)[0] for k in xi])
+    assert np.abs(phihat - quad).max() / quad.max() < 1e-11
+    # device polynomial: float32 coefficients, error at float32 resolution
+    assert np.abs(poly - ref).max() < 1e-7
+
+
+def _slices(*rows):
+    from paper_2304_12934_amd._lib import NrSlice
+    arr = (NrSlice * len(rows))()
+    for i, r in enumerate(rows):
+        arr[i] = NrSlice(*r)
+    return arr
+
+
+def _create(L, rows, angles, width=7):
+    from paper_2304_12934_amd._lib import NrNufft
+    h = ctypes.c_void_p()
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    st = L.nr_plan_create(_slices(*rows), len(rows), ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          ctypes.byref(NrNufft(2.0, width, 0.0)), ctypes.byref(h))
+    return st, h
+
+
+def test_plan_validation_status_codes(L):
+    from paper_2304_12934_amd import _lib
+    ang = np.linspace(0, np.pi, 10, endpoint=False)
+    assert _create(L, [(127, 128, 10, 0, 0, 0)], ang)[0] == _lib.NR_INVALID_ARG       # odd N
+    assert _create(L, [(128, 6, 10, 0, 0, 0)], ang)[0] == _lib.NR_INVALID_ARG         # N_t < 8
+    assert _create(L, [(128, 128, 0, 0, 0, 0)], ang)[0] == _lib.NR_INVALID_ARG        # no angles
+    assert _create(L, [(48, 128, 10, 0, 0, 0)], ang)[0] == _lib.NR_UNSUPPORTED_SIZE   # G = 96
+    assert _create(L, [(128, 96, 10, 0, 0, 0)], ang)[0] == _lib.NR_UNSUPPORTED_SIZE   # N_t = 96
+    assert _create(L, [(128, 128, 10, 0, 0, 0)], ang, width=9)[0] == _lib.NR_UNSUPPORTED_SIZE
+    bad = ang.copy()
+    bad[3] = np.nan
+    assert _create(L, [(128, 128, 10, 0, 0, 0)], bad)[0] == _lib.NR_INVALID_ARG
+    assert L.nr_last_error()
+    st, h = _create(L, [(128, 128, 10, 0, 0, 0)], ang)
+    assert st == _lib.NR_OK
+    # binding a NULL workspace is refused before any device work
+    assert L.nr_plan_bind(h, None, 0, None) == _lib.NR_INVALID_ARG
+    assert L.radon_fwd(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == _lib.NR_INVALID_ARG  # not bound
+    L.nr_plan_destroy(h)
+
+
+def test_plan_info_and_workspace(L):
+    from paper_2304_12934_amd import _lib
+    ang = np.linspace(0, np.pi, 90, endpoint=False)
+    st, h = _create(L, [(128, 128, 90, 0, 0, 0), (128, 128, 90, 128 * 128, 90 * 128, 0)], ang)
+    assert st == _lib.NR_OK
+    info = (ctypes.c_int64 * 5)()
+    assert L.nr_plan_info(h, 1, info, 5) == _lib.NR_OK
+    G, tiles, entries, items, degree = list(info)
+    assert G == 256 and degree == 9
+    assert entries >= 90 * 64          # every point j >= 1 sits in at least one tile
+    assert items >= tiles
+    nbytes = ctypes.c_size_t()
+    assert L.nr_plan_workspace_bytes(h, ctypes.byref(nbytes)) == _lib.NR_OK
+    # at least the extended half-plane grid (G/2 + 1 + 8 rows of G + 8 complex)
+    assert nbytes.value >= (G // 2 + 9) * (G + 8) * 8
+    L.nr_plan_destroy(h)
