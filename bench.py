@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the NUFFT Radon forward + adjoint projector on one MI355X.
+
+One step = forward projection and adjoint (back-projection) of every slice
+of a stack: by default 32 slices of 2560 x 2560 random-ellipse phantoms
+(20 ellipses each), 1024 angles uniform in [0, pi), 2560 detector bins,
+float32 data with complex64 intermediates.  Inputs are resident in device
+memory before timing starts.
+
+Prints one JSON line: slices/s, per-stage kernel times from HIP events
+recorded on the library's stream during the timed steps, the roofline of
+the dominant kernel against the algorithmic byte model, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+adj Radon slices/s (2560², 1024 angles) & % HBM roofline; MBIR iters/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(n: int, nd: int, na: int, tile_entries: int) -> dict:
+    """Algorithmic HBM bytes of one launch (one slice) of each stage.
+
+    Each pass reads and writes its operands once at storage precision, with
+    the half-plane grid of G(G/2+1) complex64 values (G = 2N) and H = N_t/2+1
+    points per half-line.  The interpolation reads the inscribed disc of the
+    grid (pi/4 of it).  The spreading also reads its 4-byte point list.
+    """
+    G = 2 * n
+    H = nd // 2 + 1
+    half = G // 2 + 1
+    return {
+        "fwd_rows": 4 * n * n + 8 * n * half,
+        "fwd_cols": 8 * n * half + 8 * G * half,
+        "fwd_interp": 8 * G * half * math.pi / 4 + 4 * na * nd,
+        "adj_radial": 4 * na * nd + 8 * na * H,
+        "spread": 8 * na * H + 4 * tile_entries + 8 * G * half,
+        "adj_cols": 8 * G * half + 8 * n * half,
+        "adj_rows": 8 * n * half + 4 * n * n,
+    }
+
+
+def model_bytes_per_slice(n: int, nd: int, na: int) -> float:
+    """Unfused pipeline model (forward + adjoint) of one slice."""
+    G = 2 * n
+    H = nd // 2 + 1
+    half = G // 2 + 1
+    fwd = 4 * n * n + 16 * n * half + 8 * G * half * (1 + math.pi / 4) + 16 * na * H + 4 * na * nd
+    adj = 4 * na * nd + 16 * na * H + 16 * G * half + 16 * n * half + 4 * n * n
+    return fwd + adj
+
+
+def cpu_baseline(f64_slice, angles, n_det: int, n_angles_total: int, sample_angles: int) -> dict:
+    """FP64 oracle on the host: forward + adjoint of one slice on a subset of angles."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import radon as ora
+    idx = np.linspace(0, len(angles) - 1, sample_angles).round().astype(int)
+    sub = angles[idx]
+    t0 = time.perf_counter()
+    s = ora.radon_fwd(f64_slice, sub, n_det)
+    ora.radon_adj(s, sub, f64_slice.shape[0])
+    dt = time.perf_counter() - t0
+    per_slice = dt * n_angles_total / sample_angles
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    return {
+        "value": 1.0 / per_slice,
+        "unit": "slices/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"1 slice {f64_slice.shape[0]}^2, forward+adjoint on {sample_angles} of {n_angles_total} "
+                   f"angles in {dt:.1f} s, extrapolated linearly in the angle count"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--slices", type=int, default=32)
+    ap.add_argument("--n", type=int, default=2560)
+    ap.add_argument("--angles", type=int, default=1024)
+    ap.add_argument("--ellipses", type=int, default=20)
+    ap.add_argument("--cpu-angles", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the projector shards along z with no exchange, see the design notes", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import Plan
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, nd, na, S = args.n, args.n, args.angles, args.slices
+    angles = synth.uniform_angles(na)
+
+    t_gen = time.perf_counter()
+    vol = torch.empty((S, n, n), dtype=torch.float32, device=dev)
+    for z in range(S):
+        vol[z] = synth.ellipse_phantom(2, z, n, args.ellipses, device=dev).to(torch.float32)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] phantoms {S} x {n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    plan = Plan.uniform_stack(n, nd, angles, S, device=dev)
+    info = plan.info(0)
+    sino = torch.empty(plan.sino_shape(), dtype=torch.float32, device=dev)
+    back = torch.empty(plan.vol_shape(), dtype=torch.float32, device=dev)
+
+    def step():
+        plan.fwd(vol, sino)
+        plan.adj(sino, back)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
+
+    if not args.no_profile:
+        plan.profile(True)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = e0.elapsed_time(e1)
+    stages = plan.profile_read() if not args.no_profile else {}
+    plan.profile(False)
+    ms_per_step = ms_total / args.steps
+    value = S * args.steps / (ms_total / 1e3)
+    print(f"[bench] {args.steps} steps in {ms_total:.1f} ms (wall {wall:.2f} s)", file=sys.stderr, flush=True)
+
+    sb = stage_bytes(n, nd, na, info["tile_entries"])
+    stage_report = {}
+    for name, (ms, launches) in stages.items():
+        per = ms / launches
+        gbs = sb[name] / (per * 1e-3) / 1e9 if name in sb else None
+        stage_report[name] = {"ms_per_launch": round(per, 5), "launches": launches,
+                              "GB_per_s": round(gbs, 1) if gbs else None}
+    roofline = None
+    if stages:
+        dom = max((k for k in stages if k in sb), key=lambda k: stages[k][0])
+        per_ms = stages[dom][0] / stages[dom][1]
+        achieved = sb[dom] / (per_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": int(sb[dom]), "ms_per_launch": round(per_ms, 5)}
+
+    mb = model_bytes_per_slice(n, nd, na)
+    step_gbs = mb * S / (ms_per_step * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
+        f64 = vol[0].double().cpu().numpy()
+        cpu = cpu_baseline(f64, angles, nd, na, args.cpu_angles)
+
+    try:
+        sha = subprocess.run(["git", "rev-parse", "--short", "HEAD"], cwd=ROOT, capture_output=True,
+                             text=True).stdout.strip() or None
+    except Exception:
+        sha = None
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{S} slices {n}x{n} random ellipses ({args.ellipses} each), {na} angles in [0,pi), "
+                               f"{nd} bins, forward+adjoint per slice",
+                   "slices": S, "n": n, "n_angles": na, "n_det": nd, "kernel_width": 7, "oversampling": 2,
+                   "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "model_bytes_per_slice": int(mb),
+        "step_GB_per_s_vs_model": round(step_gbs, 1),
+        "step_frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
+        "stages": stage_report,
+        "wall_s": round(wall, 3),
+        "git": sha,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

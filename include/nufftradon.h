@@ -112,6 +112,16 @@ nr_status nr_plan_destroy(nr_plan* plan);
  * 1 = one thread per point with global atomics (a slow cross-check). */
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
 
+/* Stage timing for measurement.  While enabled, every stage launch of
+ * radon_fwd / radon_adj / mbir_step is bracketed by two HIP events on the
+ * caller's stream.  nr_plan_profile_read waits for the last recorded event
+ * and returns, per stage, the summed milliseconds and the launch count, then
+ * forgets the records.  Stages: 0 forward rows, 1 forward columns, 2
+ * interpolation + radial transform, 3 adjoint radial transform, 4 spreading,
+ * 5 adjoint columns, 6 adjoint rows, 7 residual, 8 prior, 9 MBIR update. */
+nr_status nr_plan_profile(nr_plan* plan, int32_t enable);
+nr_status nr_plan_profile_read(nr_plan* plan, double* ms, int64_t* launches, int32_t n_stages);
+
 /* s = R f for every slice of the plan (Sec. 2, eq. "fourier_radon" via the
  * type-2 NUFFT).  d_vol: float32 slices at vol_off; d_sino: float32
  * sinograms at sino_off, overwritten.  Device pointers. */

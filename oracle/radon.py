@@ -108,8 +108,9 @@ def radon_adj(y: np.ndarray, angles: np.ndarray, n: int) -> np.ndarray:
         px = 2.0 * np.pi * np.outer(k, x) * np.cos(th)       # phase of conj(Ex)
         py = 2.0 * np.pi * np.outer(k, yc) * np.sin(th)      # phase of conj(Ey)
         B = Yhat[a][:, None] * (np.cos(py) + 1j * np.sin(py))  # [l, iy]
-        # Re(B^T conj(Ex)) with conj(Ex) = cos(px) + i sin(px)
-        g += B.real.T @ np.cos(px) - B.imag.T @ np.sin(px)
+        # Re(B^T conj(Ex)) with conj(Ex) = cos(px) + i sin(px); contiguous
+        # copies of the transposed parts keep the products on BLAS
+        g += np.ascontiguousarray(B.real.T) @ np.cos(px) - np.ascontiguousarray(B.imag.T) @ np.sin(px)
     return g
 
 

@@ -57,6 +57,8 @@ SIGNATURES = {
     "nr_plan_bind": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "nr_plan_destroy": (c_int32, [c_void_p]),
     "nr_plan_tune": (c_int32, [c_void_p, c_char_p, c_int64]),
+    "nr_plan_profile": (c_int32, [c_void_p, c_int32]),
+    "nr_plan_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
     "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,

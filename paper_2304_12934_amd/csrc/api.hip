@@ -6,15 +6,35 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "nufftradon.h"
 #include "plan.hpp"
 #include "prior_kernels.hpp"
 #include "radon_kernels.hpp"
 
+// Opt-in stage timing: a pair of events recorded around every stage launch
+// on the caller's stream, read back (and synchronised) on request.
+enum { kStageResidual = int(nrk::Stage::Count), kStagePrior, kStageUpdate, kStageCount };
+
+struct StageEvents {
+  int stage;
+  hipEvent_t start, stop;
+};
+
 struct nr_plan {
   nr::Plan p;
   int spread_mode = 0;   // 0: LDS tiles, 1: global atomics (reference)
+  bool profiling = false;
+  std::vector<StageEvents> recorded;
+  std::vector<hipEvent_t> pool;
+  ~nr_plan() {
+    for (auto& r : recorded) {
+      hipEventDestroy(r.start);
+      hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -77,6 +97,30 @@ nrk::SliceArgs slice_args(const nr::Plan& p, int s) {
   a.tile_h = g.tile_h;
   a.tiles_x = g.tiles_x;
   return a;
+}
+
+hipEvent_t take_event(nr_plan* plan) {
+  if (!plan->pool.empty()) {
+    hipEvent_t e = plan->pool.back();
+    plan->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `launch` (which enqueues one stage on `st`), bracketed by events when profiling.
+template <class F>
+hipError_t timed(nr_plan* plan, int stage, hipStream_t st, F&& launch) {
+  if (!plan->profiling) return launch();
+  hipEvent_t a = take_event(plan), b = take_event(plan);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  plan->recorded.push_back({stage, a, b});
+  return e;
 }
 
 nr_status check_bound(const nr_plan* plan) {
@@ -190,6 +234,35 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
   return fail(NR_INVALID_ARG, std::string("unknown tuning key ") + key);
 }
 
+nr_status nr_plan_profile(nr_plan* plan, int32_t enable) {
+  if (!plan) return fail(NR_INVALID_ARG, "plan is NULL");
+  plan->profiling = enable != 0;
+  return NR_OK;
+}
+
+nr_status nr_plan_profile_read(nr_plan* plan, double* ms, int64_t* launches, int32_t n_stages) {
+  if (!plan || !ms || !launches || n_stages < 0) return fail(NR_INVALID_ARG, "plan/ms/launches is NULL");
+  for (int i = 0; i < n_stages; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  hipError_t err = hipSuccess;
+  if (!plan->recorded.empty()) err = hipEventSynchronize(plan->recorded.back().stop);
+  for (auto& r : plan->recorded) {
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, r.start, r.stop);
+    if (r.stage < n_stages) {
+      ms[r.stage] += t;
+      launches[r.stage] += 1;
+    }
+    plan->pool.push_back(r.start);
+    plan->pool.push_back(r.stop);
+  }
+  plan->recorded.clear();
+  if (err != hipSuccess) return hip_fail(err, "nr_plan_profile_read");
+  return NR_OK;
+}
+
 nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream stream) {
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_sino) return fail(NR_INVALID_ARG, "d_vol/d_sino is NULL");
@@ -200,8 +273,13 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
     nrk::SliceArgs a = slice_args(p, s);
     a.vol_in = d_vol + p.slices[size_t(s)].vol_off;
     a.sino_out = d_sino + p.slices[size_t(s)].sino_off;
-    const hipError_t e = nrk::launch_fwd(a, kb, p.kb.W, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "radon_fwd launch");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    for (nrk::Stage stage : {nrk::Stage::FwdRows, nrk::Stage::FwdCols, nrk::Stage::FwdInterp}) {
+      const hipError_t e = timed(plan, int(stage), st, [&] {
+        return nrk::launch_stage(stage, a, kb, p.kb.W, plan->spread_mode, st);
+      });
+      if (e != hipSuccess) return hip_fail(e, "radon_fwd launch");
+    }
   }
   return NR_OK;
 }
@@ -216,9 +294,13 @@ nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream 
     nrk::SliceArgs a = slice_args(p, s);
     a.sino_in = d_sino + p.slices[size_t(s)].sino_off;
     a.vol_out = d_vol + p.slices[size_t(s)].vol_off;
-    const hipError_t e =
-        nrk::launch_adj(a, kb, p.kb.W, plan->spread_mode, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "radon_adj launch");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    for (nrk::Stage stage : {nrk::Stage::AdjRadial, nrk::Stage::Spread, nrk::Stage::AdjCols, nrk::Stage::AdjRows}) {
+      const hipError_t e = timed(plan, int(stage), st, [&] {
+        return nrk::launch_stage(stage, a, kb, p.kb.W, plan->spread_mode, st);
+      });
+      if (e != hipSuccess) return hip_fail(e, "radon_adj launch");
+    }
   }
   return NR_OK;
 }
@@ -267,15 +349,18 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (nr_status s = radon_fwd(plan, d_y, d_scratch, stream)) return s;
-  hipError_t e = nrk::launch_residual(d_scratch, d_b, sino_total, st);
+  hipError_t e = timed(plan, kStageResidual, st, [&] { return nrk::launch_residual(d_scratch, d_b, sino_total, st); });
   if (e != hipSuccess) return hip_fail(e, "mbir_step residual");
   if (nr_status s = radon_adj(plan, d_scratch, d_grad, stream)) return s;
   if (prior->lambda > 0.0f) {
-    e = nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, prior_args(prior), 1.0f, st);
+    const nrk::PriorArgs pa = prior_args(prior);
+    e = timed(plan, kStagePrior, st, [&] { return nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, pa, 1.0f, st); });
     if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
   }
-  e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(nz) * n * n, params->inv_L, params->nonneg,
-                              d_state, st);
+  e = timed(plan, kStageUpdate, st, [&] {
+    return nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(nz) * n * n, params->inv_L, params->nonneg,
+                                   d_state, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "mbir_step update");
   return NR_OK;
 }

@@ -146,8 +146,9 @@ double KaiserBessel::max_poly_error() const {
 void build_spread_bins(const Plan& plan, Geom& g) {
   const int W = plan.kb.W;
   const int na = g.key.n_angles;
-  g.tile_w = std::min(64, g.cols);
-  g.tile_h = std::min(32, g.rows);
+  // fixed tile shape (the kernel is compiled for it); edge tiles are partial
+  g.tile_w = 64;
+  g.tile_h = 32;
   g.tiles_x = (g.cols + g.tile_w - 1) / g.tile_w;
   g.tiles_y = (g.rows + g.tile_h - 1) / g.tile_h;
   const int ntiles = g.tiles_x * g.tiles_y;

@@ -435,76 +435,86 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
 #define NR_LENGTHS(X) \
   X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(80) X(160) X(320) X(640) X(1280) X(2560) X(5120)
 
-hipError_t launch_fwd(const SliceArgs& a, const KBArgs& kb, int W, hipStream_t st) {
-  const int G = a.G, Nt = a.Nt;
-  hipError_t e = hipSuccess;
-  switch (G) {
-#define NR_CASE(l)                                                                          \
-  case l:                                                                                   \
-    hipLaunchKernelGGL(k_fwd_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a);        \
-    hipLaunchKernelGGL(k_fwd_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a);      \
-    break;
-    NR_LENGTHS(NR_CASE)
-#undef NR_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int nb = (a.na + 1) / 2;
-  switch (Nt) {
-#define NR_CASE(l)                                                                                  \
-  case l:                                                                                           \
-    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
-    if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
-    if (W == 8) hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
-    break;
-    NR_LENGTHS(NR_CASE)
-#undef NR_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_adj(const SliceArgs& a, const KBArgs& kb, int W, int spread_mode, hipStream_t st) {
+hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W, int spread_mode,
+                        hipStream_t st) {
   const int G = a.G, Nt = a.Nt;
   const int nb = (a.na + 1) / 2;
-  switch (Nt) {
-#define NR_CASE(l)                                                                 \
-  case l:                                                                          \
-    hipLaunchKernelGGL(k_adj_radial<l>, dim3(nb), dim3(fft_threads(l)), 0, st, a); \
-    break;
-    NR_LENGTHS(NR_CASE)
+  switch (stage) {
+    case Stage::FwdRows:
+      switch (G) {
+#define NR_CASE(l) \
+  case l: hipLaunchKernelGGL(k_fwd_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a); break;
+        NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  hipError_t e;
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (spread_mode == 1) {
-    const size_t n4 = size_t(a.rows) * a.cols / 2;
-    hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(a.ext), n4);
-    const int np = a.na * a.H;
-    const dim3 g((np + 255) / 256);
-    if (W == 6) hipLaunchKernelGGL(k_spread_atomic<6>, g, dim3(256), 0, st, a, kb);
-    if (W == 7) hipLaunchKernelGGL(k_spread_atomic<7>, g, dim3(256), 0, st, a, kb);
-    if (W == 8) hipLaunchKernelGGL(k_spread_atomic<8>, g, dim3(256), 0, st, a, kb);
-  } else {
-    if (a.tile_w != 64 || a.tile_h != 32) return hipErrorInvalidValue;
-    if (a.n_zero > 0) hipLaunchKernelGGL(k_spread_zero, dim3(a.n_zero), dim3(256), 0, st, a);
-    if (W == 6) hipLaunchKernelGGL((k_spread_tiles<6, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-    if (W == 7) hipLaunchKernelGGL((k_spread_tiles<7, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-    if (W == 8) hipLaunchKernelGGL((k_spread_tiles<8, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-  }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  switch (G) {
-#define NR_CASE(l)                                                                     \
-  case l:                                                                              \
-    hipLaunchKernelGGL(k_adj_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); \
-    hipLaunchKernelGGL(k_adj_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a);   \
-    break;
-    NR_LENGTHS(NR_CASE)
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case Stage::FwdCols:
+      switch (G) {
+#define NR_CASE(l) \
+  case l: hipLaunchKernelGGL(k_fwd_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); break;
+        NR_LENGTHS(NR_CASE)
 #undef NR_CASE
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case Stage::FwdInterp:
+      switch (Nt) {
+#define NR_CASE(l)                                                                                          \
+  case l:                                                                                                   \
+    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb);     \
+    else if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
+    else hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb);             \
+    break;
+        NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case Stage::AdjRadial:
+      switch (Nt) {
+#define NR_CASE(l) \
+  case l: hipLaunchKernelGGL(k_adj_radial<l>, dim3(nb), dim3(fft_threads(l)), 0, st, a); break;
+        NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case Stage::Spread:
+      if (spread_mode == 1) {
+        const size_t n4 = size_t(a.rows) * a.cols / 2;
+        hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(a.ext), n4);
+        const int np = a.na * a.H;
+        const dim3 g((np + 255) / 256);
+        if (W == 6) hipLaunchKernelGGL(k_spread_atomic<6>, g, dim3(256), 0, st, a, kb);
+        else if (W == 7) hipLaunchKernelGGL(k_spread_atomic<7>, g, dim3(256), 0, st, a, kb);
+        else hipLaunchKernelGGL(k_spread_atomic<8>, g, dim3(256), 0, st, a, kb);
+      } else {
+        if (a.tile_w != 64 || a.tile_h != 32) return hipErrorInvalidValue;
+        if (a.n_zero > 0) hipLaunchKernelGGL(k_spread_zero, dim3(a.n_zero), dim3(256), 0, st, a);
+        if (W == 6) hipLaunchKernelGGL((k_spread_tiles<6, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+        else if (W == 7) hipLaunchKernelGGL((k_spread_tiles<7, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+        else hipLaunchKernelGGL((k_spread_tiles<8, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
+      }
+      break;
+    case Stage::AdjCols:
+      switch (G) {
+#define NR_CASE(l) \
+  case l: hipLaunchKernelGGL(k_adj_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); break;
+        NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    case Stage::AdjRows:
+      switch (G) {
+#define NR_CASE(l) \
+  case l: hipLaunchKernelGGL(k_adj_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a); break;
+        NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+        default: return hipErrorInvalidValue;
+      }
+      break;
     default:
       return hipErrorInvalidValue;
   }

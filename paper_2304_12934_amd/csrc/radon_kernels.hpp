@@ -35,8 +35,11 @@ struct KBArgs {
   float c[8 * 11];
 };
 
-hipError_t launch_fwd(const SliceArgs& a, const KBArgs& kb, int W, hipStream_t st);
+// Stages of the forward chain (FwdRows, FwdCols, FwdInterp) and of the
+// adjoint chain (AdjRadial, Spread, AdjCols, AdjRows), launched in that order.
+enum class Stage : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, Count };
+
 // spread_mode 0: LDS tiles (default), 1: plain global atomics (reference)
-hipError_t launch_adj(const SliceArgs& a, const KBArgs& kb, int W, int spread_mode, hipStream_t st);
+hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W, int spread_mode, hipStream_t st);
 
 }  // namespace nrk

@@ -143,6 +143,22 @@ class Plan:
             check(lib().radon_adj(self._h, _ptr(sino), _ptr(out), _stream(self.device)), "radon_adj")
         return out
 
+    STAGES = ("fwd_rows", "fwd_cols", "fwd_interp", "adj_radial", "spread", "adj_cols", "adj_rows",
+              "residual", "prior", "mbir_update")
+
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every stage launch with HIP events on the launch stream."""
+        check(lib().nr_plan_profile(self._h, 1 if enable else 0), "nr_plan_profile")
+
+    def profile_read(self) -> dict:
+        """Per stage: (total ms, launches) since the last read; waits for the recorded events."""
+        n = len(self.STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        with torch.cuda.device(self.device):
+            check(lib().nr_plan_profile_read(self._h, ms, cnt, n), "nr_plan_profile_read")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(self.STAGES) if cnt[i]}
+
     def tune(self, key: str, value: int) -> None:
         check(lib().nr_plan_tune(self._h, key.encode(), int(value)), "nr_plan_tune")
 
