@@ -98,6 +98,8 @@ def main() -> int:
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one device-to-device copy of MIB MiB before timing (a counter reference)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +126,14 @@ def main() -> int:
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] phantoms {S} x {n}^2 in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
+        del src, dst
 
     plan = Plan.uniform_stack(n, nd, angles, S, device=dev)
     info = plan.info(0)

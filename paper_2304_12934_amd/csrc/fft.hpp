@@ -175,11 +175,26 @@ struct Dft<5, INV> {
 };
 
 // ---------------------------------------------------------------------------
+// LDS buffer with one padding element per 16: strided Stockham writes of
+// the early passes then spread over the 32 four-byte banks
+// ---------------------------------------------------------------------------
+
+template <int L>
+constexpr int lds_elems() {
+  return L + L / 16 + 1;
+}
+
+struct Lds {
+  float2* p;
+  __device__ __forceinline__ float2& operator[](int i) const { return p[i + (i >> 4)]; }
+};
+
+// ---------------------------------------------------------------------------
 // one Stockham pass and the whole transform
 // ---------------------------------------------------------------------------
 
 template <int L, int T, int P, bool INV>
-__device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_pass(Lds s, const float2* __restrict__ tw, int tid) {
   constexpr int R = radix_of(L, P);
   constexpr int Ns = span_before(L, P);
   constexpr int NB = L / R;
@@ -217,7 +232,7 @@ __device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ t
 }
 
 template <int L, int T, bool INV, int P = 0>
-__device__ __forceinline__ void fft_passes(float2* s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_passes(Lds s, const float2* __restrict__ tw, int tid) {
   if constexpr (P < num_passes(L)) {
     fft_pass<L, T, P, INV>(s, tw, tid);
     fft_passes<L, T, INV, P + 1>(s, tw, tid);
@@ -229,7 +244,7 @@ __device__ __forceinline__ void fft_passes(float2* s, const float2* __restrict__
 // The caller must have synchronised after filling s; on return s holds the
 // result and the workgroup has synchronised.
 template <int L, int T, bool INV>
-__device__ __forceinline__ void fft_lds(float2* s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_lds(Lds s, const float2* __restrict__ tw, int tid) {
   static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
   fft_passes<L, T, INV>(s, tw, tid);
 }

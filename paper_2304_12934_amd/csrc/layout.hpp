@@ -9,5 +9,6 @@ struct SpreadItem {
   int32_t begin, end;   // range in the geometry's point-index list
   int32_t flags;        // bit 0: tile shared by several items (accumulate with atomics)
                         // bit 1: this item also spreads the k = 0 point of every angle
+  int32_t bound;        // most points of this item that touch any one cell of the tile
 };
 enum { kItemAtomic = 1, kItemDC = 2 };

@@ -188,6 +188,7 @@ void build_spread_bins(const Plan& plan, Geom& g) {
   const int dc0 = d0 + g.G / 2 + plan.colpad, dc1 = dc0 + W - 1;
   g.items.clear();
   g.zero_tiles.clear();
+  std::vector<int32_t> cell_count(size_t(g.tile_w) * g.tile_h);
   for (int t = 0; t < ntiles; ++t) {
     const int b = g.tile_start[t], e = g.tile_start[t + 1];
     const int n_items = std::max(1, (e - b + chunk - 1) / chunk);
@@ -198,8 +199,21 @@ void build_spread_bins(const Plan& plan, Geom& g) {
     for (int k = 0; k < n_items; ++k) {
       const int ib = b + int((int64_t(e - b) * k) / n_items);
       const int ie = b + int((int64_t(e - b) * (k + 1)) / n_items);
+      // largest number of this item's points that touch one cell: bounds the
+      // magnitude of every cell's sum for the kernel's fixed-point scale
+      std::fill(cell_count.begin(), cell_count.end(), 0);
+      int cmax = 0;
+      for (int q = ib; q < ie; ++q) {
+        const int a = g.pts[size_t(q)] / g.H, j = g.pts[size_t(q)] % g.H;
+        const int g0x = int(std::ceil(double(j) * g.gxy[2 * a] - halfW));
+        const int g0y = int(std::ceil(double(j) * g.gxy[2 * a + 1] - halfW));
+        const int rr0 = g0x + plan.halo - ty * g.tile_h, cc0 = g0y + g.G / 2 + plan.colpad - tx * g.tile_w;
+        for (int i = std::max(0, rr0); i < std::min(g.tile_h, rr0 + W); ++i)
+          for (int l = std::max(0, cc0); l < std::min(g.tile_w, cc0 + W); ++l)
+            cmax = std::max(cmax, ++cell_count[size_t(i) * g.tile_w + l]);
+      }
       const int flags = (n_items > 1 ? kItemAtomic : 0) | (has_dc && k == 0 ? kItemDC : 0);
-      g.items.push_back({t, ib, ie, flags});
+      g.items.push_back({t, ib, ie, flags, cmax + ((flags & kItemDC) ? 1 : 0) + 1});
     }
   }
   // heaviest items first so the long ones start early

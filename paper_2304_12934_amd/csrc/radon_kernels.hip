@@ -84,7 +84,8 @@ __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(SliceArgs a) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int N = a.N;
   const int iy0 = 2 * blockIdx.x;
@@ -132,7 +133,8 @@ __device__ __forceinline__ void store_row(float2* row, int colpad, int n, float2
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(SliceArgs a) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int N = a.N;
   const int qx = blockIdx.x;
@@ -188,7 +190,8 @@ __device__ __forceinline__ float2 interp_point(const SliceArgs& a, const KBArgs&
 template <int L, int W>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBArgs kb) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
   const bool has1 = a1 < a.na;
@@ -222,7 +225,8 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBAr
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(SliceArgs a) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
   const bool has1 = a1 < a.na;
@@ -262,25 +266,33 @@ __global__ __launch_bounds__(256) void k_spread_zero(SliceArgs a) {
 }
 
 // One work item = one grid tile (TH rows x TW columns) and a range of the
-// points whose footprint touches it.  The tile accumulates in LDS with LDS
-// float atomics; single-item tiles are then stored plainly (covering every
-// cell, zeros included), shared tiles are added with global atomics.
+// points whose footprint touches it.  The tile accumulates in LDS in 32-bit
+// fixed point with integer LDS atomics: on gfx950 float LDS atomics run
+// about 40x slower than integer ones.  The item's scale q = 2^30/(M b), with
+// M the largest |component| of its values and b the most of its points that
+// touch any one cell (from the plan), bounds every cell's final sum by 2^30
+// (|phi| <= 1), so the wrapped 32-bit partial sums are exact modulo 2^32 and
+// the final sum is exact up to the rounding of each contribution to 1/q.  Single-item tiles are then stored
+// plainly (every cell, zeros included); shared tiles are added with global
+// float atomics.
 template <int W, int TW, int TH>
 __global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
-  __shared__ float acc_re[TH * TW];
-  __shared__ float acc_im[TH * TW];
+  // row stride TW + 1: lanes stepping along a tile column hit different banks
+  constexpr int TS = TW + 1;
+  __shared__ int acc_re[TH * TS];
+  __shared__ int acc_im[TH * TS];
   __shared__ float red[256];
   const SpreadItem it = a.items[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int c = tid; c < TH * TW; c += 256) {
-    acc_re[c] = 0.f;
-    acc_im[c] = 0.f;
+  for (int c = tid; c < TH * TS; c += 256) {
+    acc_re[c] = 0;
+    acc_im[c] = 0;
   }
   const int r0 = (it.tile / a.tiles_x) * TH, c0 = (it.tile % a.tiles_x) * TW;
   const int rbase = a.halo - r0, cbase = a.G / 2 + a.colpad - c0;
-  __syncthreads();
+  // k = 0 of every angle sits at the origin: their sum is spread once
+  float dc = 0.f;
   if (it.flags & 2) {
-    // k = 0 of every angle sits at the origin: sum them, spread once
     float sum = 0.f;
     for (int ang = tid; ang < a.na; ang += 256) sum += a.yh[size_t(ang) * a.H].x;
     red[tid] = sum;
@@ -289,24 +301,57 @@ __global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid < W * W) {
-      int g0x, g0y;
-      float wx[W], wy[W];
-      point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
-      const int i = tid / W, l = tid % W;
-      const int rr = g0x + i + rbase, cc = g0y + l + cbase;
-      if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) atomicAdd(&acc_re[rr * TW + cc], red[0] * wx[i] * wy[l]);
-    }
+    dc = red[0];
+    __syncthreads();
+  }
+  // fixed-point scale of this item
+  float m = 0.f;
+  for (int e = it.begin + tid; e < it.end; e += 256) {
+    const float2 v = a.yh[a.pts[e]];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const float mmax = fmaxf(red[0], fabsf(dc));
+  const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
+  if ((it.flags & 2) && tid < W * W) {
+    int g0x, g0y;
+    float wx[W], wy[W];
+    point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
+    const int i = tid / W, l = tid % W;
+    const int rr = g0x + i + rbase, cc = g0y + l + cbase;
+    if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(q * dc * wx[i] * wy[l]));
   }
   for (int e = it.begin + tid; e < it.end; e += 256) {
     const int pid = a.pts[e];
     const int ang = pid / a.H, j = pid - ang * a.H;
     float2 v = a.yh[pid];
     if (a.flip[ang]) v.y = -v.y;
+    v.x *= q;
+    v.y *= q;
     int g0x, g0y;
     float wx[W], wy[W];
     point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
     const int rr0 = g0x + rbase, cc0 = g0y + cbase;
+    if (rr0 >= 0 && rr0 + W <= TH && cc0 >= 0 && cc0 + W <= TW) {
+      // whole footprint inside the tile
+      int* pre = acc_re + rr0 * TS + cc0;
+      int* pim = acc_im + rr0 * TS + cc0;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        const float vx = wx[i] * v.x, vy = wx[i] * v.y;
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+          atomicAdd(pre + i * TS + l, __float2int_rn(vx * wy[l]));
+          atomicAdd(pim + i * TS + l, __float2int_rn(vy * wy[l]));
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < W; ++i) {
       const int rr = rr0 + i;
@@ -316,22 +361,25 @@ __global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
       for (int l = 0; l < W; ++l) {
         const int cc = cc0 + l;
         if (cc < 0 || cc >= TW) continue;
-        atomicAdd(&acc_re[rr * TW + cc], vx * wy[l]);
-        atomicAdd(&acc_im[rr * TW + cc], vy * wy[l]);
+        atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(vx * wy[l]));
+        atomicAdd(&acc_im[rr * TS + cc], __float2int_rn(vy * wy[l]));
       }
     }
   }
   __syncthreads();
   const bool shared_tile = it.flags & 1;
+  const float inv_q = q > 0.f ? 1.0f / q : 0.f;
   for (int c = tid; c < TH * TW; c += 256) {
-    const int r = r0 + c / TW, cc = c0 + c % TW;
+    const int rl = c / TW, cl = c % TW;
+    const int r = r0 + rl, cc = c0 + cl;
     if (r >= a.rows || cc >= a.cols) continue;
     float2* dst = a.ext + size_t(r) * a.cols + cc;
+    const float re = float(acc_re[rl * TS + cl]) * inv_q, im = float(acc_im[rl * TS + cl]) * inv_q;
     if (shared_tile) {
-      atomicAdd(&dst->x, acc_re[c]);
-      atomicAdd(&dst->y, acc_im[c]);
+      atomicAdd(&dst->x, re);
+      atomicAdd(&dst->y, im);
     } else {
-      *dst = make_float2(acc_re[c], acc_im[c]);
+      *dst = make_float2(re, im);
     }
   }
 }
@@ -373,7 +421,8 @@ __device__ __forceinline__ float2 load_folded(const float2* row, int colpad, int
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(SliceArgs a) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int qx = blockIdx.x;
   const int halo = a.halo, colpad = a.colpad, cols = a.cols, N = a.N;
@@ -400,7 +449,8 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(SliceArgs a) {
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
   constexpr int T = fft_threads(L);
-  __shared__ float2 s[L];
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int N = a.N;
   const int iy0 = 2 * blockIdx.x;
