@@ -88,7 +88,9 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(SliceArgs a) {
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int N = a.N;
-  const int iy0 = 2 * blockIdx.x;
+  const int pair = xcd_block(N / 2);   // neighbouring row pairs share L2 lines of T
+  if (pair < 0) return;
+  const int iy0 = 2 * pair;
   const float* __restrict__ f0 = a.vol_in + size_t(iy0) * N;
   const float d0 = a.deapod[iy0], d1 = a.deapod[iy0 + 1];
   // x = ix - N/2 sits at index x mod L
@@ -193,7 +195,9 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBAr
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
+  const int pair = xcd_block((a.na + 1) / 2);   // neighbouring angles read the same grid lines
+  if (pair < 0) return;
+  const int a0 = 2 * pair, a1 = a0 + 1;
   const bool has1 = a1 < a.na;
   const float inv = 1.0f / float(L);
   // pack the Hermitian completions of both half-lines: Z = X + iY
@@ -453,7 +457,9 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   const int N = a.N;
-  const int iy0 = 2 * blockIdx.x;
+  const int pair = xcd_block(N / 2);   // neighbouring row pairs share L2 lines of T
+  if (pair < 0) return;
+  const int iy0 = 2 * pair;
   const float4* __restrict__ in = reinterpret_cast<const float4*>(a.T);
   // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
   for (int q = tid; q <= L / 2; q += T) {
@@ -493,7 +499,7 @@ hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W
     case Stage::FwdRows:
       switch (G) {
 #define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_fwd_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a); break;
+  case l: hipLaunchKernelGGL(k_fwd_rows<l>, dim3(xcd_grid(a.N / 2)), dim3(fft_threads(l)), 0, st, a); break;
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
         default: return hipErrorInvalidValue;
@@ -512,9 +518,9 @@ hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W
       switch (Nt) {
 #define NR_CASE(l)                                                                                          \
   case l:                                                                                                   \
-    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb);     \
-    else if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb); \
-    else hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(nb), dim3(fft_threads(l)), 0, st, a, kb);             \
+    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb);     \
+    else if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb); \
+    else hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb);             \
     break;
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
@@ -559,7 +565,7 @@ hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W
     case Stage::AdjRows:
       switch (G) {
 #define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_adj_rows<l>, dim3(a.N / 2), dim3(fft_threads(l)), 0, st, a); break;
+  case l: hipLaunchKernelGGL(k_adj_rows<l>, dim3(xcd_grid(a.N / 2)), dim3(fft_threads(l)), 0, st, a); break;
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
         default: return hipErrorInvalidValue;
