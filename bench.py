@@ -86,6 +86,58 @@ def cpu_baseline(f64_slice, angles, n_det: int, n_angles_total: int, sample_angl
     }
 
 
+def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
+    """MBIR iterations/s on a 3D ellipsoid volume with Poisson data: the plain
+    per-iteration entry (mbir_step) against the autograd path (DataFidelityFn +
+    QGGMRFFn backward, then the update kernel), and the reconstruction error of
+    each after `iters` iterations (relative L2 inside the inscribed cylinder)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import MBIR, Plan, Prior, power_lipschitz
+
+    vol = synth.ellipsoid_volume(4, n, nz, 20, device=dev).to(torch.float32).contiguous()
+    plan = Plan.uniform_stack(n, n, synth.uniform_angles(na), nz, device=dev)
+    b_true = plan.fwd(vol)
+    scale = 2.0 / float(b_true.max())          # largest attenuation 2 (transmission ~13.5%)
+    vol *= scale
+    b_true *= scale
+    b = torch.as_tensor(synth.poisson_log_data(b_true, synth.rng_for(4, 1), 1.0e4), dtype=torch.float32,
+                        device=dev).contiguous()
+    prior = Prior(lam=1.0)
+    L = power_lipschitz(plan, 30) + prior.lipschitz()
+    x_ = (torch.arange(n, device=dev, dtype=torch.float32) - n // 2)
+    mask = ((x_[None, :] ** 2 + x_[:, None] ** 2) <= (n / 2) ** 2).to(torch.float32)
+
+    def err(x):
+        d = (x - vol) * mask
+        return float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(vol * mask))
+
+    out = {"volume": f"{nz} x {n}^2 random ellipsoids (20)", "n_angles": na, "data": "Poisson, 1e4 photons/bin",
+           "iterations": iters, "prior": "qGGMRF p=1.2 sigma=1/0.7 c=1e-4 lambda=1, 26 neighbours"}
+    for name, fn in (("plain", "step"), ("autograd", "step_autograd")):
+        m = MBIR(plan, b, prior, L)
+        step = getattr(m, fn)
+        for _ in range(2):                        # warm-up (iterates restart below)
+            step()
+        m = MBIR(plan, b, prior, L)
+        step = getattr(m, fn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(timed):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for _ in range(iters - timed):
+            step()
+        torch.cuda.synchronize()
+        out[f"iters_per_s_{name}"] = round(timed / dt, 2)
+        out[f"recon_rel_err_{name}"] = round(err(m.x), 5)
+        out[f"restarts_{name}"] = m.restarts
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +150,11 @@ def main() -> int:
     ap.add_argument("--cpu-angles", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
+    ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
+    ap.add_argument("--mbir-n", type=int, default=1280)
+    ap.add_argument("--mbir-slices", type=int, default=64)
+    ap.add_argument("--mbir-angles", type=int, default=256)
+    ap.add_argument("--mbir-iters", type=int, default=50)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of MIB MiB before timing (a counter reference)")
     args = ap.parse_args()
@@ -188,10 +245,18 @@ def main() -> int:
     mb = model_bytes_per_slice(n, nd, na)
     step_gbs = mb * S / (ms_per_step * 1e-3) / 1e9
 
+    mbir = None
+    if not args.no_mbir:
+        del vol, sino, back, plan
+        torch.cuda.empty_cache()
+        print("[bench] MBIR leg ...", file=sys.stderr, flush=True)
+        mbir = mbir_leg(dev, args.mbir_n, args.mbir_slices, args.mbir_angles, args.mbir_iters, 10)
+        print(f"[bench] MBIR {mbir}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
-        f64 = vol[0].double().cpu().numpy()
+        f64 = synth.ellipse_phantom(2, 0, n, args.ellipses).numpy()
         cpu = cpu_baseline(f64, angles, nd, na, args.cpu_angles)
 
     try:
@@ -222,6 +287,7 @@ def main() -> int:
         "step_GB_per_s_vs_model": round(step_gbs, 1),
         "step_frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
         "stages": stage_report,
+        "mbir": mbir,
         "wall_s": round(wall, 3),
         "git": sha,
     }

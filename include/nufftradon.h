@@ -132,6 +132,13 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
  * overwritten.  Device pointers. */
 nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream);
 
+/* Data term of the objective (Sec. 3, eq. "objfn" with G = 1/2 ||R f - b||^2):
+ * d_r = R f - b (sinogram layout, overwritten) and, when d_value is not NULL,
+ * *d_value = 1/2 sum r^2 as one float64 on the device.  Its gradient is
+ * radon_adj(d_r) (eq. "gradient"). */
+nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, float* d_r, double* d_value,
+                         nr_stream stream);
+
 /* qGGMRF prior (Sec. 3, eqs. "reg2"/"reg3") on a [nz][n][n] float32 volume:
  *   H(f) = lambda sum_m sum_{n in N26(m)} w_mn rho((f_m - f_n)/sigma),
  *   rho(u) = u^2/(c + |u|^(2-p)),
@@ -169,6 +176,14 @@ typedef struct {
 nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
                     const float* d_b, float* d_x, float* d_x_prev, float* d_y, float* d_grad,
                     float* d_scratch, double* d_state, nr_stream stream);
+
+/* The update half of mbir_step for a gradient computed elsewhere (e.g. by
+ * autograd through radon_fwd / radon_adj / qggmrf_grad): given g = grad
+ * Phi(y) in d_grad, performs the restart test, the momentum update and
+ * x_prev <- x, x <- x', y <- y' over `count` float32 elements, with d_state
+ * as for mbir_step.  Device pointers; no host synchronisation. */
+nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
+                      int64_t count, double* d_state, nr_stream stream);
 
 /* Host-only helpers (no device needed), used to test the plan's tables.
  * nr_kb_eval: for the plan-independent kernel with (width, beta), evaluates

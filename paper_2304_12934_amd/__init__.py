@@ -6,6 +6,7 @@ C ABI in ``include/nufftradon.h``); this package is its Python binding.
 
 from .radon import (  # noqa: F401
     MBIR,
+    DataFidelityFn,
     Plan,
     Prior,
     QGGMRFFn,
@@ -16,5 +17,5 @@ from .radon import (  # noqa: F401
     qggmrf_grad,
 )
 
-__all__ = ["Plan", "SliceGeometry", "Prior", "RadonFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
+__all__ = ["Plan", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
            "power_lipschitz", "kb_eval"]

@@ -61,10 +61,13 @@ SIGNATURES = {
     "nr_plan_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
     "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "radon_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,
                               c_void_p]),
     "mbir_step": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mbir_update": (c_int32, [POINTER(NrMbir), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                              c_void_p]),
     "nr_kb_eval": (c_int32, [c_int32, c_double, c_int32, POINTER(c_double), POINTER(c_double),
                              POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     "nr_plan_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), c_int32]),

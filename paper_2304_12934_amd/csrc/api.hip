@@ -365,6 +365,36 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   return NR_OK;
 }
 
+nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, float* d_r, double* d_value,
+                         nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!d_vol || !d_b || !d_r) return fail(NR_INVALID_ARG, "radon_residual: NULL argument");
+  const nr::Plan& p = plan->p;
+  size_t sino_total = 0;
+  for (const nr_slice& sl : p.slices)
+    sino_total = std::max(sino_total, size_t(sl.sino_off) + size_t(sl.n_angles) * sl.n_det);
+  if (nr_status s = radon_fwd(plan, d_vol, d_r, stream)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = timed(plan, kStageResidual, st, [&] {
+    return d_value ? nrk::launch_residual_norm(d_r, d_b, sino_total, d_value, st)
+                   : nrk::launch_residual(d_r, d_b, sino_total, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "radon_residual launch");
+  return NR_OK;
+}
+
+nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
+                      int64_t count, double* d_state, nr_stream stream) {
+  if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state) return fail(NR_INVALID_ARG, "mbir_update: NULL argument");
+  if (count < 1) return fail(NR_INVALID_ARG, "mbir_update: count must be >= 1");
+  if (!(params->inv_L > 0.0f)) return fail(NR_INVALID_ARG, "inv_L must be > 0");
+  if (nr_status st = pending_error("before mbir_update")) return st;
+  const hipError_t e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(count), params->inv_L,
+                                               params->nonneg, d_state, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mbir_update launch");
+  return NR_OK;
+}
+
 nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u, const double* xi,
                      double* phi, double* phihat, double* phi_poly) {
   if (width < 6 || width > 8 || count < 0) return fail(NR_INVALID_ARG, "width must be 6..8, count >= 0");

@@ -106,6 +106,25 @@ __global__ void k_residual(float* __restrict__ s, const float* __restrict__ b, s
     s[i] -= b[i];
 }
 
+// r = s - b in place and value += 1/2 sum r^2 (float64 block sums)
+__global__ __launch_bounds__(256) void k_residual_norm(float* __restrict__ s, const float* __restrict__ b,
+                                                       size_t count, double* value) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
+    const float r = s[i] - b[i];
+    s[i] = r;
+    acc += double(r) * double(r);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(value, 0.5 * red[0]);
+}
+
 // <g, x' - x> with x' = y - g/L (clamped at 0 when nonneg); non-finite flag
 __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, const float* __restrict__ y,
                                                   const float* __restrict__ g, size_t count, float inv_L,
@@ -174,6 +193,12 @@ hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int
 
 hipError_t launch_residual(float* s, const float* b, size_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_residual, dim3(2048), dim3(256), 0, st, s, b, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_norm(float* s, const float* b, size_t count, double* value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, value, 0.0);
+  hipLaunchKernelGGL(k_residual_norm, dim3(2048), dim3(256), 0, st, s, b, count, value);
   return hipGetLastError();
 }
 

@@ -308,14 +308,20 @@ __global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
     dc = red[0];
     __syncthreads();
   }
-  // fixed-point scale of this item
+  // fixed-point scale of this item; a non-finite value (which the integer
+  // conversion would turn into 0) poisons the whole tile with NaN instead
+  __shared__ int nonfinite;
+  if (tid == 0) nonfinite = !isfinite(dc);
   float m = 0.f;
+  bool bad = false;
   for (int e = it.begin + tid; e < it.end; e += 256) {
     const float2 v = a.yh[a.pts[e]];
     m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    bad |= !isfinite(v.x) || !isfinite(v.y);
   }
   red[tid] = m;
   __syncthreads();
+  if (bad) nonfinite = 1;
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
     __syncthreads();
@@ -372,7 +378,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
   }
   __syncthreads();
   const bool shared_tile = it.flags & 1;
-  const float inv_q = q > 0.f ? 1.0f / q : 0.f;
+  const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
   for (int c = tid; c < TH * TW; c += 256) {
     const int rl = c / TW, cl = c % TW;
     const int r = r0 + rl, cc = c0 + cl;

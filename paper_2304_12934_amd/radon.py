@@ -237,6 +237,33 @@ class RadonFn(torch.autograd.Function):
         return ctx.plan.adj(g.contiguous()), None
 
 
+class DataFidelityFn(torch.autograd.Function):
+    """``1/2 ||R x - b||^2`` (float64 scalar); the residual and the half-norm run
+    in the library, the backward is the hand-written adjoint of the residual."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, plan: Plan, b: torch.Tensor) -> torch.Tensor:
+        _require(b, plan.sino_numel, plan.device, "b")
+        xc = x.contiguous()
+        _require(xc, plan.vol_numel, plan.device, "x")
+        r = torch.empty(plan.sino_shape(), dtype=torch.float32, device=plan.device)
+        val = torch.empty(1, dtype=torch.float64, device=plan.device)
+        with torch.cuda.device(plan.device):
+            check(lib().radon_residual(plan._h, _ptr(xc), _ptr(b), _ptr(r), _ptr(val), _stream(plan.device)),
+                  "radon_residual")
+        ctx.plan = plan
+        ctx.save_for_backward(r)
+        return val[0]
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (r,) = ctx.saved_tensors
+        grad = ctx.plan.adj(r)
+        if g.numel() != 1 or float(g) != 1.0:
+            grad = grad * g.to(grad.dtype)
+        return grad, None, None
+
+
 class QGGMRFFn(torch.autograd.Function):
     """``H(x)`` (float64 scalar) whose backward is the hand-written prior gradient."""
 
@@ -293,6 +320,22 @@ class MBIR:
         for _ in range(iters):
             self.step()
         return self.x
+
+    def step_autograd(self) -> None:
+        """Same iteration with the gradient from autograd: ``DataFidelityFn``
+        (backward = the hand-written adjoint of the residual) and ``QGGMRFFn``
+        (backward = the prior kernel), then the update kernel."""
+        y = self.y.detach().requires_grad_(True)
+        loss = DataFidelityFn.apply(y, self.plan, self.b)
+        if self.prior.lam > 0:
+            loss = loss + QGGMRFFn.apply(y, self.prior)
+        loss.backward()
+        self.grad.copy_(y.grad)
+        with torch.cuda.device(self.plan.device):
+            check(lib().mbir_update(ctypes.byref(self.params), _ptr(self.x), _ptr(self.x_prev), _ptr(self.y),
+                                    _ptr(self.grad), self.x.numel(), _ptr(self.state), _stream(self.plan.device)),
+                  "mbir_update")
+        self.k += 1
 
     @property
     def restarts(self) -> int:
