@@ -138,6 +138,56 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
     return out
 
 
+def batched_leg(dev, count: int, reps: int) -> dict:
+    """Uneven stack: `count` slices with N in {512, 1024, 2048}, angle counts
+    U[128, 1500] (half sparse with a random offset, half limited-view), N_t = N.
+    Forward + adjoint of the whole stack as one HIP-graph launch of the batched
+    plan, against per-slice launches (one slice per batch, no graph)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import Plan, SliceGeometry
+
+    rng = synth.rng_for(3, 0)
+    geoms = []
+    for i in range(count):
+        n = int(rng.choice([512, 1024, 2048]))
+        na = int(rng.integers(128, 1501))
+        ang = synth.sparse_angles(rng, na) if i % 2 == 0 else synth.limited_view_angles(rng, na)
+        geoms.append(SliceGeometry(n, n, ang))
+    from paper_2304_12934_amd.autotune import autotune
+    tuning = autotune(geoms, device=dev, reps=2, use_cache=False)
+    plan = Plan(geoms, device=dev, tuning=tuning)
+    per = Plan(geoms, device=dev, tuning={"batch": 1})
+    vol = torch.empty(plan.vol_numel, dtype=torch.float32, device=dev)
+    for i, g in enumerate(geoms):
+        o = plan.vol_offsets[i]
+        vol[o:o + g.n * g.n] = synth.ellipse_phantom(3, i, g.n, 20, device=dev).to(torch.float32).reshape(-1)
+    sino = torch.empty(plan.sino_numel, dtype=torch.float32, device=dev)
+    back = torch.empty(plan.vol_numel, dtype=torch.float32, device=dev)
+    graph = plan.capture("fwd+adj", vol, sino, back)
+
+    def t(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_graph = t(graph.launch)
+    t_per = t(lambda: (per.fwd(vol, sino), per.adj(sino, back)))
+    info = plan.info()
+    sizes = {n: sum(1 for g in geoms if g.n == n) for n in (512, 1024, 2048)}
+    return {"slices": count, "sizes": sizes, "angles_total": int(sum(len(g.angles) for g in geoms)),
+            "batched_graph_slices_per_s": round(count / t_graph, 1),
+            "per_slice_slices_per_s": round(count / t_per, 1),
+            "speedup": round(t_per / t_graph, 3), "tuning": tuning, "batches": info["batches"], "slots": info["slots"],
+            "launches_per_pass": info["launches"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +201,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
     ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-stack leg")
+    ap.add_argument("--batched-slices", type=int, default=96)
     ap.add_argument("--mbir-n", type=int, default=1280)
     ap.add_argument("--mbir-slices", type=int, default=64)
     ap.add_argument("--mbir-angles", type=int, default=256)
@@ -227,20 +279,23 @@ def main() -> int:
     print(f"[bench] {args.steps} steps in {ms_total:.1f} ms (wall {wall:.2f} s)", file=sys.stderr, flush=True)
 
     sb = stage_bytes(n, nd, na, info["tile_entries"])
+    per_launch_slices = S / max(1, info["batches"])      # slices covered by one stage launch
     stage_report = {}
     for name, (ms, launches) in stages.items():
-        per = ms / launches
-        gbs = sb[name] / (per * 1e-3) / 1e9 if name in sb else None
-        stage_report[name] = {"ms_per_launch": round(per, 5), "launches": launches,
-                              "GB_per_s": round(gbs, 1) if gbs else None}
+        per_slice = ms / (args.steps * S)
+        gbs = sb[name] / (per_slice * 1e-3) / 1e9 if name in sb else None
+        stage_report[name] = {"ms_per_launch": round(ms / launches, 5), "ms_per_slice": round(per_slice, 5),
+                              "launches": launches, "GB_per_s": round(gbs, 1) if gbs else None}
     roofline = None
     if stages:
         dom = max((k for k in stages if k in sb), key=lambda k: stages[k][0])
         per_ms = stages[dom][0] / stages[dom][1]
-        achieved = sb[dom] / (per_ms * 1e-3) / 1e9
+        bytes_launch = sb[dom] * per_launch_slices
+        achieved = bytes_launch / (per_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "bytes_per_launch": int(sb[dom]), "ms_per_launch": round(per_ms, 5)}
+                    "bytes_per_launch": int(bytes_launch), "ms_per_launch": round(per_ms, 5),
+                    "slices_per_launch": per_launch_slices}
 
     mb = model_bytes_per_slice(n, nd, na)
     step_gbs = mb * S / (ms_per_step * 1e-3) / 1e9
@@ -252,6 +307,13 @@ def main() -> int:
         print("[bench] MBIR leg ...", file=sys.stderr, flush=True)
         mbir = mbir_leg(dev, args.mbir_n, args.mbir_slices, args.mbir_angles, args.mbir_iters, 10)
         print(f"[bench] MBIR {mbir}", file=sys.stderr, flush=True)
+
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        print("[bench] uneven-stack leg ...", file=sys.stderr, flush=True)
+        batched = batched_leg(dev, args.batched_slices, 3)
+        print(f"[bench] uneven {batched}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -288,6 +350,7 @@ def main() -> int:
         "step_frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
         "stages": stage_report,
         "mbir": mbir,
+        "uneven_stack": batched,
         "wall_s": round(wall, 3),
         "git": sha,
     }

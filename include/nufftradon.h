@@ -107,9 +107,22 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_workspace, size_t bytes, nr_stream
 
 nr_status nr_plan_destroy(nr_plan* plan);
 
-/* Set a tuning parameter of a plan (no effect on results beyond float32
- * summation order).  Keys: "spread_mode" 0 = LDS-tiled spreading (default),
- * 1 = one thread per point with global atomics (a slow cross-check). */
+/* Set an execution parameter of a plan; none changes results beyond float32
+ * rounding of the spreading sums.  Keys:
+ *   "tile_w", "tile_h"  spreading tile (64x32 default; 32x32, 64x64, 128x32)
+ *   "chunk"             most points per spreading work item (1024 default)
+ *   "batch"             most slices per batch (0: no limit): each stage kernel
+ *                       runs once per batch (and FFT length) over all its
+ *                       slices; the workspace holds the scratch of the
+ *                       largest batch
+ *   "batch_mb"          scratch budget of one batch in MiB (160 default:
+ *                       one 2560^2 slice, whose grids then stay in the 256 MB
+ *                       last-level cache between stages; a slice larger than
+ *                       the budget runs alone)
+ *   "spread_mode"       0 = LDS-tiled spreading (default), 1 = one thread per
+ *                       point with global float atomics (a slow cross-check)
+ * Changing any key but spread_mode unbinds the plan: query
+ * nr_plan_workspace_bytes and call nr_plan_bind again. */
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
 
 /* Stage timing for measurement.  While enabled, every stage launch of
@@ -185,6 +198,20 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
 nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
                       int64_t count, double* d_state, nr_stream stream);
 
+/* Graphs: a whole forward/adjoint pass or a run of MBIR steps captured once
+ * (on a private stream) into a HIP graph and replayed with one launch.  The
+ * buffers are bound at capture; the plan must outlive the graph and stay
+ * bound.  what: 1 = radon_fwd(d_vol_in -> d_sino), 2 = radon_adj(d_sino ->
+ * d_vol_out), 3 = both in that order. */
+typedef struct nr_graph nr_graph;
+nr_status nr_graph_capture_radon(nr_plan* plan, int32_t what, const float* d_vol_in, float* d_sino,
+                                 float* d_vol_out, nr_graph** out);
+nr_status nr_graph_capture_mbir(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, const float* d_b,
+                                float* d_x, float* d_x_prev, float* d_y, float* d_grad, float* d_scratch,
+                                double* d_state, int32_t iters, nr_graph** out);
+nr_status nr_graph_launch(nr_graph* graph, nr_stream stream);
+nr_status nr_graph_destroy(nr_graph* graph);
+
 /* Host-only helpers (no device needed), used to test the plan's tables.
  * nr_kb_eval: for the plan-independent kernel with (width, beta), evaluates
  * phi(u) (normalised to phi(0)=1) at u[i] with the float64 series, phihat
@@ -193,9 +220,11 @@ nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float*
 nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u, const double* xi,
                      double* phi, double* phihat, double* phi_poly);
 
-/* Describe how a plan splits work: fills counts for slice `index`:
+/* Describe how a plan splits work: fills up to 8 counts for slice `index`:
  * info[0] = oversampled grid G, info[1] = spreading tiles, info[2] = tile
- * point entries, info[3] = spreading work items, info[4] = polynomial degree. */
+ * point entries, info[3] = spreading work items, info[4] = polynomial degree,
+ * info[5] = scratch slots (slices per batch), info[6] = batches,
+ * info[7] = kernel launches of one forward + adjoint pass. */
 nr_status nr_plan_info(const nr_plan* plan, int32_t index, int64_t* info, int32_t count);
 
 #ifdef __cplusplus

@@ -7,6 +7,7 @@ C ABI in ``include/nufftradon.h``); this package is its Python binding.
 from .radon import (  # noqa: F401
     MBIR,
     DataFidelityFn,
+    Graph,
     Plan,
     Prior,
     QGGMRFFn,
@@ -17,5 +18,5 @@ from .radon import (  # noqa: F401
     qggmrf_grad,
 )
 
-__all__ = ["Plan", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
+__all__ = ["Plan", "Graph", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
            "power_lipschitz", "kb_eval"]

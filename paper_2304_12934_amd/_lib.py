@@ -68,6 +68,11 @@ SIGNATURES = {
                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mbir_update": (c_int32, [POINTER(NrMbir), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                               c_void_p]),
+    "nr_graph_capture_radon": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]),
+    "nr_graph_capture_mbir": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_void_p)]),
+    "nr_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "nr_graph_destroy": (c_int32, [c_void_p]),
     "nr_kb_eval": (c_int32, [c_int32, c_double, c_int32, POINTER(c_double), POINTER(c_double),
                              POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     "nr_plan_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), c_int32]),

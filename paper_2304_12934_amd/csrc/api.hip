@@ -15,7 +15,10 @@
 
 // Opt-in stage timing: a pair of events recorded around every stage launch
 // on the caller's stream, read back (and synchronised) on request.
-enum { kStageResidual = int(nrk::Stage::Count), kStagePrior, kStageUpdate, kStageCount };
+enum {
+  kStageFwdRows = 0, kStageFwdCols, kStageFwdInterp, kStageAdjRadial, kStageSpread, kStageAdjCols,
+  kStageAdjRows, kStageResidual, kStagePrior, kStageUpdate, kStageCount
+};
 
 struct StageEvents {
   int stage;
@@ -24,16 +27,25 @@ struct StageEvents {
 
 struct nr_plan {
   nr::Plan p;
-  int spread_mode = 0;   // 0: LDS tiles, 1: global atomics (reference)
   bool profiling = false;
   std::vector<StageEvents> recorded;
   std::vector<hipEvent_t> pool;
+  std::vector<SliceDesc> host_descs;
   ~nr_plan() {
     for (auto& r : recorded) {
-      hipEventDestroy(r.start);
-      hipEventDestroy(r.stop);
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.stop);
     }
-    for (hipEvent_t e : pool) hipEventDestroy(e);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct nr_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~nr_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
 };
 
@@ -50,53 +62,11 @@ nr_status hip_fail(hipError_t e, const char* where) {
   return fail(NR_HIP_ERROR, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-template <class T>
-const T* ws_ptr(const nr::Plan& p, size_t off) {
-  return reinterpret_cast<const T*>(static_cast<const char*>(p.d_ws) + off);
-}
-template <class T>
-T* ws_mut(const nr::Plan& p, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(p.d_ws) + off);
-}
-
 nrk::KBArgs kb_args(const nr::Plan& p) {
   nrk::KBArgs kb;
   std::memset(&kb, 0, sizeof(kb));
   std::memcpy(kb.c, p.kb.coef.data(), p.kb.coef.size() * sizeof(float));
   return kb;
-}
-
-nrk::SliceArgs slice_args(const nr::Plan& p, int s) {
-  const nr_slice& sl = p.slices[size_t(s)];
-  const nr::Geom& g = p.geoms[size_t(p.slice_geom[size_t(s)])];
-  nrk::SliceArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.N = sl.n;
-  a.Nt = sl.n_det;
-  a.na = sl.n_angles;
-  a.G = g.G;
-  a.H = g.H;
-  a.rows = g.rows;
-  a.cols = g.cols;
-  a.halo = p.halo;
-  a.colpad = p.colpad;
-  a.deapod = ws_ptr<float>(p, p.off_deapod.at(sl.n));
-  a.tw_G = ws_ptr<float2>(p, p.off_twiddle.at(g.G));
-  a.tw_Nt = ws_ptr<float2>(p, p.off_twiddle.at(sl.n_det));
-  a.gxy = ws_ptr<double>(p, g.off_gxy);
-  a.flip = ws_ptr<int>(p, g.off_flip);
-  a.T = ws_mut<float2>(p, p.off_slot + p.slot_t);
-  a.ext = ws_mut<float2>(p, p.off_slot + p.slot_ext);
-  a.yh = ws_mut<float2>(p, p.off_slot + p.slot_yh);
-  a.pts = ws_ptr<int>(p, g.off_pts);
-  a.items = ws_ptr<SpreadItem>(p, g.off_items);
-  a.zero_tiles = ws_ptr<int>(p, g.off_zero);
-  a.n_items = int(g.items.size());
-  a.n_zero = int(g.zero_tiles.size());
-  a.tile_w = g.tile_w;
-  a.tile_h = g.tile_h;
-  a.tiles_x = g.tiles_x;
-  return a;
 }
 
 hipEvent_t take_event(nr_plan* plan) {
@@ -135,6 +105,126 @@ nr_status pending_error(const char* where) {
   return NR_OK;
 }
 
+nr_status ensure_layout(nr_plan* plan) {
+  std::string err;
+  const nr_status st = nr::layout_plan(plan->p, err);
+  return st == NR_OK ? NR_OK : fail(st, err);
+}
+
+int stage_event_id(nr::Stage s) {
+  switch (s) {
+    case nr::Stage::FwdRows: return kStageFwdRows;
+    case nr::Stage::FwdCols: return kStageFwdCols;
+    case nr::Stage::FwdInterp: return kStageFwdInterp;
+    case nr::Stage::AdjRadial: return kStageAdjRadial;
+    case nr::Stage::SpreadZero:
+    case nr::Stage::Spread: return kStageSpread;
+    case nr::Stage::AdjCols: return kStageAdjCols;
+    case nr::Stage::AdjRows: return kStageAdjRows;
+    default: return kStageCount;
+  }
+}
+
+// Enqueue the stage launches of every batch (forward or adjoint chain).
+nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol_out, const float* sino_in,
+                    float* sino_out, hipStream_t st, const char* where) {
+  const nr::Plan& p = plan->p;
+  const nrk::KBArgs kb = kb_args(p);
+  const char* base = static_cast<const char*>(p.d_ws);
+  nrk::LaunchArgs a{};
+  a.descs = reinterpret_cast<const SliceDesc*>(base + p.off_desc);
+  a.halo = p.halo;
+  a.colpad = p.colpad;
+  a.vol_in = vol_in;
+  a.vol_out = vol_out;
+  a.sino_in = sino_in;
+  a.sino_out = sino_out;
+  for (const nr::Batch& bt : p.batches) {
+    for (const nr::StageLaunch& sl : forward ? bt.fwd : bt.adj) {
+      const bool spread = sl.stage == nr::Stage::Spread || sl.stage == nr::Stage::SpreadZero;
+      hipError_t e = hipSuccess;
+      if (spread && p.tune.spread_mode == 1) {
+        // reference spreading, one slice at a time
+        if (sl.stage == nr::Stage::SpreadZero) continue;
+        for (int s : bt.slices) {
+          e = timed(plan, kStageSpread, st, [&] {
+            return nrk::launch_spread_reference(a.descs, s, plan->host_descs[size_t(s)], p.halo, p.colpad, kb,
+                                                p.kb.W, st);
+          });
+          if (e != hipSuccess) break;
+        }
+      } else {
+        nrk::LaunchArgs la = a;
+        la.work = reinterpret_cast<const WorkItem*>(base + p.off_work + sl.work_off);
+        la.n_work = sl.n_work;
+        e = timed(plan, stage_event_id(sl.stage), st, [&] {
+          return nrk::launch_stage(static_cast<nrk::StageKind>(int(sl.stage)), sl.L, la, kb, p.kb.W,
+                                   p.tune.tile_w, p.tune.tile_h, st);
+        });
+      }
+      if (e != hipSuccess) return hip_fail(e, where);
+    }
+  }
+  return NR_OK;
+}
+
+size_t sino_extent(const nr::Plan& p) {
+  size_t n = 0;
+  for (const nr_slice& sl : p.slices) n = std::max(n, size_t(sl.sino_off) + size_t(sl.n_angles) * sl.n_det);
+  return n;
+}
+
+nr_status check_prior(const nr_prior* prior) {
+  if (!prior) return fail(NR_INVALID_ARG, "prior is NULL");
+  if (!(prior->p >= 1.0f && prior->p <= 2.0f) || !(prior->sigma > 0.0f) || !(prior->c > 0.0f) ||
+      !(prior->lambda >= 0.0f))
+    return fail(NR_INVALID_ARG, "prior needs 1 <= p <= 2, sigma > 0, c > 0, lambda >= 0");
+  return NR_OK;
+}
+
+nrk::PriorArgs prior_args(const nr_prior* p) {
+  return nrk::PriorArgs{p->p, p->sigma, p->c, p->lambda, p->w_face, p->w_edge, p->w_corner};
+}
+
+// Runs `enqueue(stream)` under stream capture and instantiates the graph.
+template <class F>
+nr_status capture(nr_plan* plan, nr_graph** out, F&& enqueue) {
+  if (!out) return fail(NR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (nr_status st = pending_error("before graph capture")) return st;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "graph capture stream");
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  nr_graph* g = new (std::nothrow) nr_graph;
+  nr_status status = g ? NR_OK : fail(NR_INTERNAL, "out of host memory");
+  if (status == NR_OK) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      status = hip_fail(e, "hipStreamBeginCapture");
+    } else {
+      status = enqueue(static_cast<nr_stream>(cs));
+      hipGraph_t graph = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+      g->graph = graph;
+      if (status == NR_OK && e2 != hipSuccess) status = hip_fail(e2, "hipStreamEndCapture");
+      if (status == NR_OK) {
+        const hipError_t e3 = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) status = hip_fail(e3, "hipGraphInstantiate");
+      }
+    }
+  }
+  plan->profiling = prof;
+  (void)hipStreamDestroy(cs);
+  if (status != NR_OK) {
+    delete g;
+    return status;
+  }
+  *out = g;
+  return NR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -154,7 +244,7 @@ const char* nr_status_str(nr_status s) {
 
 const char* nr_last_error(void) { return g_err.c_str(); }
 
-const char* nr_version(void) { return "nufftradon 0.1 (gfx950)"; }
+const char* nr_version(void) { return "nufftradon 0.2 (gfx950)"; }
 
 nr_status nr_plan_create(const nr_slice* slices, int32_t n_slices, const double* angles_host,
                          const nr_nufft* params, nr_plan** out) {
@@ -164,7 +254,8 @@ nr_status nr_plan_create(const nr_slice* slices, int32_t n_slices, const double*
   if (!p) return fail(NR_INTERNAL, "out of host memory");
   try {
     std::string err;
-    const nr_status st = nr::build_plan(slices, n_slices, angles_host, params, p->p, err);
+    nr_status st = nr::build_plan(slices, n_slices, angles_host, params, p->p, err);
+    if (st == NR_OK) st = nr::layout_plan(p->p, err);
     if (st != NR_OK) {
       delete p;
       return fail(st, err);
@@ -179,6 +270,7 @@ nr_status nr_plan_create(const nr_slice* slices, int32_t n_slices, const double*
 
 nr_status nr_plan_workspace_bytes(const nr_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return fail(NR_INVALID_ARG, "plan/bytes is NULL");
+  if (nr_status st = ensure_layout(const_cast<nr_plan*>(plan))) return st;
   *bytes = plan->p.ws_bytes;
   return NR_OK;
 }
@@ -186,6 +278,7 @@ nr_status nr_plan_workspace_bytes(const nr_plan* plan, size_t* bytes) {
 nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream) {
   if (!plan || !d_ws) return fail(NR_INVALID_ARG, "plan/workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(NR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (nr_status st = ensure_layout(plan)) return st;
   nr::Plan& p = plan->p;
   if (bytes < p.ws_bytes)
     return fail(NR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(bytes) + " bytes, plan needs " +
@@ -193,6 +286,7 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
   if (nr_status st = pending_error("before nr_plan_bind")) return st;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(d_ws);
+  plan->host_descs = nr::slice_descs(p, base);
   auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
     if (n == 0) return hipSuccess;
     return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
@@ -210,6 +304,8 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
     if ((e = up(g.off_items, g.items.data(), g.items.size() * sizeof(SpreadItem)))) break;
     if ((e = up(g.off_zero, g.zero_tiles.data(), g.zero_tiles.size() * sizeof(int32_t)))) break;
   }
+  if (!e) e = up(p.off_desc, plan->host_descs.data(), plan->host_descs.size() * sizeof(SliceDesc));
+  if (!e) e = up(p.off_work, p.work.data(), p.work.size() * sizeof(WorkItem));
   // the host tables are read by the copies: wait here so the caller may reuse
   // or destroy the plan freely afterwards
   if (!e) e = hipStreamSynchronize(st);
@@ -226,12 +322,32 @@ nr_status nr_plan_destroy(nr_plan* plan) {
 
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
   if (!plan || !key) return fail(NR_INVALID_ARG, "plan/key is NULL");
+  nr::Tuning t = plan->p.tune;
   if (std::strcmp(key, "spread_mode") == 0) {
     if (value != 0 && value != 1) return fail(NR_INVALID_ARG, "spread_mode must be 0 (tiles) or 1 (atomics)");
-    plan->spread_mode = int(value);
-    return NR_OK;
+    plan->p.tune.spread_mode = int(value);
+    return NR_OK;   // no layout change
+  } else if (std::strcmp(key, "tile_w") == 0) {
+    t.tile_w = int(value);
+  } else if (std::strcmp(key, "tile_h") == 0) {
+    t.tile_h = int(value);
+  } else if (std::strcmp(key, "chunk") == 0) {
+    t.chunk = int(value);
+  } else if (std::strcmp(key, "batch") == 0) {
+    if (value < 0) return fail(NR_INVALID_ARG, "batch must be >= 0");
+    t.batch = int(value);
+  } else if (std::strcmp(key, "batch_mb") == 0) {
+    if (value < 0 || value > (1 << 20)) return fail(NR_INVALID_ARG, "batch_mb must be in [0, 2^20]");
+    t.batch_mb = int(value);
+  } else {
+    return fail(NR_INVALID_ARG, std::string("unknown tuning key ") + key);
   }
-  return fail(NR_INVALID_ARG, std::string("unknown tuning key ") + key);
+  // a new layout: the workspace must be queried and bound again
+  plan->p.tune = t;
+  plan->p.laid_out = false;
+  plan->p.d_ws = nullptr;
+  plan->p.d_ws_bytes = 0;
+  return NR_OK;
 }
 
 nr_status nr_plan_profile(nr_plan* plan, int32_t enable) {
@@ -267,54 +383,31 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_sino) return fail(NR_INVALID_ARG, "d_vol/d_sino is NULL");
   if (nr_status st = pending_error("before radon_fwd")) return st;
-  const nr::Plan& p = plan->p;
-  const nrk::KBArgs kb = kb_args(p);
-  for (int s = 0; s < int(p.slices.size()); ++s) {
-    nrk::SliceArgs a = slice_args(p, s);
-    a.vol_in = d_vol + p.slices[size_t(s)].vol_off;
-    a.sino_out = d_sino + p.slices[size_t(s)].sino_off;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    for (nrk::Stage stage : {nrk::Stage::FwdRows, nrk::Stage::FwdCols, nrk::Stage::FwdInterp}) {
-      const hipError_t e = timed(plan, int(stage), st, [&] {
-        return nrk::launch_stage(stage, a, kb, p.kb.W, plan->spread_mode, st);
-      });
-      if (e != hipSuccess) return hip_fail(e, "radon_fwd launch");
-    }
-  }
-  return NR_OK;
+  return run_chain(plan, true, d_vol, nullptr, nullptr, d_sino, static_cast<hipStream_t>(stream),
+                   "radon_fwd launch");
 }
 
 nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream) {
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_sino) return fail(NR_INVALID_ARG, "d_vol/d_sino is NULL");
   if (nr_status st = pending_error("before radon_adj")) return st;
-  const nr::Plan& p = plan->p;
-  const nrk::KBArgs kb = kb_args(p);
-  for (int s = 0; s < int(p.slices.size()); ++s) {
-    nrk::SliceArgs a = slice_args(p, s);
-    a.sino_in = d_sino + p.slices[size_t(s)].sino_off;
-    a.vol_out = d_vol + p.slices[size_t(s)].vol_off;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    for (nrk::Stage stage : {nrk::Stage::AdjRadial, nrk::Stage::Spread, nrk::Stage::AdjCols, nrk::Stage::AdjRows}) {
-      const hipError_t e = timed(plan, int(stage), st, [&] {
-        return nrk::launch_stage(stage, a, kb, p.kb.W, plan->spread_mode, st);
-      });
-      if (e != hipSuccess) return hip_fail(e, "radon_adj launch");
-    }
-  }
-  return NR_OK;
+  return run_chain(plan, false, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
+                   "radon_adj launch");
 }
 
-static nr_status check_prior(const nr_prior* prior) {
-  if (!prior) return fail(NR_INVALID_ARG, "prior is NULL");
-  if (!(prior->p >= 1.0f && prior->p <= 2.0f) || !(prior->sigma > 0.0f) || !(prior->c > 0.0f) ||
-      !(prior->lambda >= 0.0f))
-    return fail(NR_INVALID_ARG, "prior needs 1 <= p <= 2, sigma > 0, c > 0, lambda >= 0");
+nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, float* d_r, double* d_value,
+                         nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!d_vol || !d_b || !d_r) return fail(NR_INVALID_ARG, "radon_residual: NULL argument");
+  const size_t sino_total = sino_extent(plan->p);
+  if (nr_status s = radon_fwd(plan, d_vol, d_r, stream)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = timed(plan, kStageResidual, st, [&] {
+    return d_value ? nrk::launch_residual_norm(d_r, d_b, sino_total, d_value, st)
+                   : nrk::launch_residual(d_r, d_b, sino_total, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "radon_residual launch");
   return NR_OK;
-}
-
-static nrk::PriorArgs prior_args(const nr_prior* p) {
-  return nrk::PriorArgs{p->p, p->sigma, p->c, p->lambda, p->w_face, p->w_edge, p->w_corner};
 }
 
 nr_status qggmrf_grad(const float* d_vol, int32_t nz, int32_t n, const nr_prior* prior, float scale,
@@ -340,13 +433,12 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   const nr::Plan& p = plan->p;
   const int n = p.slices[0].n;
   const int nz = int(p.slices.size());
-  size_t sino_total = 0;
   for (int z = 0; z < nz; ++z) {
     const nr_slice& sl = p.slices[size_t(z)];
     if (sl.n != n || sl.vol_off != int64_t(z) * n * n)
       return fail(NR_INVALID_ARG, "mbir_step: slices must share N and sit at vol_off = z*N*N");
-    sino_total = std::max(sino_total, size_t(sl.sino_off) + size_t(sl.n_angles) * sl.n_det);
   }
+  const size_t sino_total = sino_extent(p);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (nr_status s = radon_fwd(plan, d_y, d_scratch, stream)) return s;
   hipError_t e = timed(plan, kStageResidual, st, [&] { return nrk::launch_residual(d_scratch, d_b, sino_total, st); });
@@ -365,33 +457,57 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   return NR_OK;
 }
 
-nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, float* d_r, double* d_value,
-                         nr_stream stream) {
-  if (nr_status st = check_bound(plan)) return st;
-  if (!d_vol || !d_b || !d_r) return fail(NR_INVALID_ARG, "radon_residual: NULL argument");
-  const nr::Plan& p = plan->p;
-  size_t sino_total = 0;
-  for (const nr_slice& sl : p.slices)
-    sino_total = std::max(sino_total, size_t(sl.sino_off) + size_t(sl.n_angles) * sl.n_det);
-  if (nr_status s = radon_fwd(plan, d_vol, d_r, stream)) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const hipError_t e = timed(plan, kStageResidual, st, [&] {
-    return d_value ? nrk::launch_residual_norm(d_r, d_b, sino_total, d_value, st)
-                   : nrk::launch_residual(d_r, d_b, sino_total, st);
-  });
-  if (e != hipSuccess) return hip_fail(e, "radon_residual launch");
-  return NR_OK;
-}
-
 nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
                       int64_t count, double* d_state, nr_stream stream) {
-  if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state) return fail(NR_INVALID_ARG, "mbir_update: NULL argument");
+  if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state)
+    return fail(NR_INVALID_ARG, "mbir_update: NULL argument");
   if (count < 1) return fail(NR_INVALID_ARG, "mbir_update: count must be >= 1");
   if (!(params->inv_L > 0.0f)) return fail(NR_INVALID_ARG, "inv_L must be > 0");
   if (nr_status st = pending_error("before mbir_update")) return st;
   const hipError_t e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(count), params->inv_L,
                                                params->nonneg, d_state, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mbir_update launch");
+  return NR_OK;
+}
+
+nr_status nr_graph_capture_radon(nr_plan* plan, int32_t what, const float* d_vol_in, float* d_sino,
+                                 float* d_vol_out, nr_graph** out) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (what < 1 || what > 3) return fail(NR_INVALID_ARG, "what must be 1 (fwd), 2 (adj) or 3 (fwd then adj)");
+  if (!d_sino || ((what & 1) && !d_vol_in) || ((what & 2) && !d_vol_out))
+    return fail(NR_INVALID_ARG, "nr_graph_capture_radon: NULL buffer");
+  return capture(plan, out, [&](nr_stream s) -> nr_status {
+    if (what & 1)
+      if (nr_status st = radon_fwd(plan, d_vol_in, d_sino, s)) return st;
+    if (what & 2)
+      if (nr_status st = radon_adj(plan, d_sino, d_vol_out, s)) return st;
+    return NR_OK;
+  });
+}
+
+nr_status nr_graph_capture_mbir(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, const float* d_b,
+                                float* d_x, float* d_x_prev, float* d_y, float* d_grad, float* d_scratch,
+                                double* d_state, int32_t iters, nr_graph** out) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (iters < 1) return fail(NR_INVALID_ARG, "iters must be >= 1");
+  return capture(plan, out, [&](nr_stream s) -> nr_status {
+    for (int k = 0; k < iters; ++k)
+      if (nr_status st = mbir_step(plan, prior, params, d_b, d_x, d_x_prev, d_y, d_grad, d_scratch, d_state, s))
+        return st;
+    return NR_OK;
+  });
+}
+
+nr_status nr_graph_launch(nr_graph* graph, nr_stream stream) {
+  if (!graph || !graph->exec) return fail(NR_INVALID_ARG, "graph is NULL");
+  if (nr_status st = pending_error("before nr_graph_launch")) return st;
+  const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return NR_OK;
+}
+
+nr_status nr_graph_destroy(nr_graph* graph) {
+  delete graph;
   return NR_OK;
 }
 
@@ -410,12 +526,15 @@ nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u,
 
 nr_status nr_plan_info(const nr_plan* plan, int32_t index, int64_t* info, int32_t count) {
   if (!plan || !info) return fail(NR_INVALID_ARG, "plan/info is NULL");
+  if (nr_status st = ensure_layout(const_cast<nr_plan*>(plan))) return st;
   const nr::Plan& p = plan->p;
   if (index < 0 || index >= int(p.slices.size())) return fail(NR_INVALID_ARG, "slice index out of range");
   const nr::Geom& g = p.geoms[size_t(p.slice_geom[size_t(index)])];
-  const int64_t v[5] = {g.G, int64_t(g.tiles_x) * g.tiles_y, int64_t(g.pts.size()), int64_t(g.items.size()),
-                        p.kb.D};
-  for (int i = 0; i < count && i < 5; ++i) info[i] = v[i];
+  int64_t launches = 0;
+  for (const nr::Batch& bt : p.batches) launches += int64_t(bt.fwd.size() + bt.adj.size());
+  const int64_t v[8] = {g.G, int64_t(g.tiles_x) * g.tiles_y, int64_t(g.pts.size()), int64_t(g.items.size()),
+                        p.kb.D, p.n_slots, int64_t(p.batches.size()), launches};
+  for (int i = 0; i < count && i < 8; ++i) info[i] = v[i];
   return NR_OK;
 }
 

@@ -190,16 +190,8 @@ struct Lds {
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
-// b % 8), each with its own L2.  Remap so that XCD x processes a contiguous
-// range of `n` logical blocks; the grid is launched with 8*ceil(n/8) blocks
-// and the block with a logical index >= n has nothing to do (returns -1).
+// b % 8), each with its own L2; grid-stride launches use multiples of 8.
 constexpr int kXcds = 8;
-__host__ __device__ constexpr int xcd_grid(int n) { return kXcds * ((n + kXcds - 1) / kXcds); }
-__device__ __forceinline__ int xcd_block(int n) {
-  const int per = (n + kXcds - 1) / kXcds;
-  const int logical = int(blockIdx.x % kXcds) * per + int(blockIdx.x / kXcds);
-  return logical < n ? logical : -1;
-}
 
 // ---------------------------------------------------------------------------
 // one Stockham pass and the whole transform

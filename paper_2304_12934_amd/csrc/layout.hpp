@@ -12,3 +12,28 @@ struct SpreadItem {
   int32_t bound;        // most points of this item that touch any one cell of the tile
 };
 enum { kItemAtomic = 1, kItemDC = 2 };
+
+// One slice as the kernels see it (device resident, filled at bind time).
+// Complex buffers are float pairs.
+struct SliceDesc {
+  int32_t N, Nt, na, G, H, rows, cols, tiles_x, n_items, n_zero, slot, pad;
+  int64_t vol_off, sino_off;      // element offsets into the caller's buffers
+  const float* deapod;            // [N] 1/phihat((i - N/2)/G)
+  const float* tw_G;              // [G] exp(-2 pi i m/G)
+  const float* tw_Nt;             // [Nt] exp(-2 pi i m/Nt)
+  const double* gxy;              // [na][2] grid step per radial index (sign-flipped)
+  const int32_t* flip;            // [na] conjugate flag
+  float* T;                       // [G/2+1][N] complex
+  float* ext;                     // [rows][cols] complex
+  float* yh;                      // [na][H] complex
+  const int32_t* pts;             // spreading point lists (tile-major)
+  const SpreadItem* items;        // spreading work items of this slice's geometry
+  const int32_t* zero_tiles;      // tiles written by several items
+};
+
+// One unit of work of a stage launch: (slice index in the plan, unit index
+// within the slice: a row pair, a column, an angle pair, a spreading item...).
+// slice < 0 marks padding.
+struct WorkItem {
+  int32_t slice, unit;
+};

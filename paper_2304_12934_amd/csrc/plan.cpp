@@ -21,6 +21,10 @@ bool fft_length_supported(int L) {
   return false;
 }
 
+bool spread_tile_supported(int w, int h) {
+  return (w == 64 && h == 32) || (w == 32 && h == 32) || (w == 64 && h == 64) || (w == 128 && h == 32);
+}
+
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel kernel
 // ---------------------------------------------------------------------------
@@ -146,9 +150,9 @@ double KaiserBessel::max_poly_error() const {
 void build_spread_bins(const Plan& plan, Geom& g) {
   const int W = plan.kb.W;
   const int na = g.key.n_angles;
-  // fixed tile shape (the kernel is compiled for it); edge tiles are partial
-  g.tile_w = 64;
-  g.tile_h = 32;
+  // tile shape from the tuning (compiled shapes only); edge tiles are partial
+  g.tile_w = plan.tune.tile_w;
+  g.tile_h = plan.tune.tile_h;
   g.tiles_x = (g.cols + g.tile_w - 1) / g.tile_w;
   g.tiles_y = (g.rows + g.tile_h - 1) / g.tile_h;
   const int ntiles = g.tiles_x * g.tiles_y;
@@ -180,7 +184,7 @@ void build_spread_bins(const Plan& plan, Geom& g) {
       for_tiles(a, j, [&](int t) { g.pts[size_t(fill[t]++)] = a * g.H + j; });
   // work items: at most `chunk` points each; tiles cut into several items
   // accumulate with atomics into a grid region cleared beforehand
-  const int chunk = 1024;
+  const int chunk = plan.tune.chunk;
   // the k = 0 point of every angle sits at the origin: it is summed over the
   // angles once and spread by the first item of each tile its footprint touches
   const int d0 = int(std::ceil(-halfW));
@@ -320,7 +324,6 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
       g.gxy[2 * a + 1] = double(g.G) * cy / double(sl.n_det);
       g.flip[a] = fl;
     }
-    build_spread_bins(plan, g);
     plan.slice_geom[s] = int(plan.geoms.size());
     geom_index[key] = int(plan.geoms.size());
     plan.geoms.push_back(std::move(g));
@@ -345,6 +348,148 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
     }
   }
 
+  return NR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches, work lists and the workspace layout
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Append `n` logical units of (slice, unit) pairs for one launch.  With
+// `xcd`, position p = 8k + x holds logical unit x*ceil(n/8) + k (padding
+// beyond n), so that a grid-stride loop over a grid that is a multiple of 8
+// gives each XCD (block b runs on XCD b % 8) a contiguous run of units.
+void append_units(std::vector<WorkItem>& out, const std::vector<WorkItem>& logical, bool xcd) {
+  if (!xcd) {
+    out.insert(out.end(), logical.begin(), logical.end());
+    return;
+  }
+  const size_t n = logical.size();
+  const size_t per = (n + 7) / 8;
+  for (size_t p = 0; p < 8 * per; ++p) {
+    const size_t x = p % 8, k = p / 8;
+    const size_t l = x * per + k;
+    out.push_back(l < n ? logical[l] : WorkItem{-1, 0});
+  }
+}
+
+}  // namespace
+
+nr_status layout_plan(Plan& plan, std::string& err) {
+  if (plan.laid_out) return NR_OK;
+  const Tuning& tu = plan.tune;
+  if (!spread_tile_supported(tu.tile_w, tu.tile_h)) {
+    err = "spreading tile " + std::to_string(tu.tile_w) + "x" + std::to_string(tu.tile_h) +
+          " is not built (64x32, 32x32, 64x64, 128x32)";
+    return NR_UNSUPPORTED_SIZE;
+  }
+  if (tu.chunk < 64 || tu.chunk > 1 << 16) {
+    err = "chunk must be in [64, 65536]";
+    return NR_INVALID_ARG;
+  }
+  for (Geom& g : plan.geoms) build_spread_bins(plan, g);
+
+  const int ns = int(plan.slices.size());
+  // per-slice scratch: T, ext and yh, each 256-byte aligned
+  auto scratch_bytes = [&](const Geom& g, size_t& t_off, size_t& ext_off, size_t& yh_off) {
+    t_off = 0;
+    ext_off = align_up(size_t(g.G / 2 + 1) * g.key.n * sizeof(f2), 256);
+    yh_off = align_up(ext_off + size_t(g.rows) * g.cols * sizeof(f2), 256);
+    return align_up(yh_off + size_t(g.key.n_angles) * g.H * sizeof(f2), 256);
+  };
+  if (tu.batch < 0 || tu.batch_mb < 0) {
+    err = "batch and batch_mb must be >= 0";
+    return NR_INVALID_ARG;
+  }
+  // batches: consecutive slices while their scratch fits the budget (a slice
+  // larger than the budget runs alone); a budget of one slot's size keeps each
+  // slice's grids resident in the 256 MB last-level cache between stages
+  const size_t budget = size_t(tu.batch_mb) << 20;
+  plan.batches.clear();
+  plan.work.clear();
+  plan.slot_area = 0;
+  plan.n_slots = 0;
+  for (int b0 = 0; b0 < ns;) {
+    Batch bt;
+    size_t used = 0;
+    for (int s = b0; s < ns; ++s) {
+      const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
+      size_t t_off, e_off, y_off;
+      const size_t need = scratch_bytes(g, t_off, e_off, y_off);
+      if (!bt.slices.empty() && (used + need > budget || (tu.batch > 0 && int(bt.slices.size()) >= tu.batch)))
+        break;
+      bt.slices.push_back(s);
+      bt.slot_off.push_back(used);
+      used += need;
+    }
+    b0 += int(bt.slices.size());
+    plan.slot_area = std::max(plan.slot_area, used);
+    plan.n_slots = std::max(plan.n_slots, int(bt.slices.size()));
+    // FFT lengths present in this batch
+    std::vector<int> Gs, Nts;
+    for (int s : bt.slices) {
+      const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
+      if (std::find(Gs.begin(), Gs.end(), g.G) == Gs.end()) Gs.push_back(g.G);
+      if (std::find(Nts.begin(), Nts.end(), g.key.n_det) == Nts.end()) Nts.push_back(g.key.n_det);
+    }
+    auto add = [&](std::vector<StageLaunch>& seq, Stage st, int L, bool by_G, bool xcd, auto&& units) {
+      std::vector<WorkItem> logical;
+      for (int s : bt.slices) {
+        const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
+        if (L > 0 && (by_G ? g.G : g.key.n_det) != L) continue;
+        units(s, g, logical);
+      }
+      if (logical.empty()) return;
+      StageLaunch sl{st, L, plan.work.size() * sizeof(WorkItem), 0};
+      append_units(plan.work, logical, xcd);
+      sl.n_work = int(plan.work.size() * sizeof(WorkItem) - sl.work_off) / int(sizeof(WorkItem));
+      seq.push_back(sl);
+    };
+    auto row_pairs = [](int s, const Geom& g, std::vector<WorkItem>& v) {
+      for (int u = 0; u < g.key.n / 2; ++u) v.push_back({s, u});
+    };
+    auto columns = [](int s, const Geom& g, std::vector<WorkItem>& v) {
+      for (int u = 0; u <= g.G / 2; ++u) v.push_back({s, u});
+    };
+    auto angle_pairs = [](int s, const Geom& g, std::vector<WorkItem>& v) {
+      for (int u = 0; u < (g.key.n_angles + 1) / 2; ++u) v.push_back({s, u});
+    };
+    for (int G : Gs) add(bt.fwd, Stage::FwdRows, G, true, true, row_pairs);
+    for (int G : Gs) add(bt.fwd, Stage::FwdCols, G, true, false, columns);
+    for (int L : Nts) add(bt.fwd, Stage::FwdInterp, L, false, true, angle_pairs);
+    for (int L : Nts) add(bt.adj, Stage::AdjRadial, L, false, false, angle_pairs);
+    add(bt.adj, Stage::SpreadZero, 0, true, false, [](int s, const Geom& g, std::vector<WorkItem>& v) {
+      for (int u = 0; u < int(g.zero_tiles.size()); ++u) v.push_back({s, u});
+    });
+    {
+      // spreading items of the whole batch, heaviest first
+      std::vector<WorkItem> logical;
+      std::vector<int> weight;
+      for (int s : bt.slices) {
+        const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
+        for (int u = 0; u < int(g.items.size()); ++u) logical.push_back({s, u});
+      }
+      std::vector<size_t> order(logical.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+      auto w = [&](size_t i) {
+        const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(logical[i].slice)])];
+        const SpreadItem& it = g.items[size_t(logical[i].unit)];
+        return it.end - it.begin;
+      };
+      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return w(a) > w(b); });
+      std::vector<WorkItem> sorted;
+      for (size_t i : order) sorted.push_back(logical[i]);
+      StageLaunch sl{Stage::Spread, 0, plan.work.size() * sizeof(WorkItem), int(sorted.size())};
+      append_units(plan.work, sorted, false);
+      bt.adj.push_back(sl);
+    }
+    for (int G : Gs) add(bt.adj, Stage::AdjCols, G, true, false, columns);
+    for (int G : Gs) add(bt.adj, Stage::AdjRows, G, true, true, row_pairs);
+    plan.batches.push_back(std::move(bt));
+  }
+
   // workspace layout
   size_t off = 0;
   for (auto& kv : plan.deapod) {
@@ -361,25 +506,61 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
     g.off_flip = off;
     off = align_up(off + g.flip.size() * sizeof(int32_t), 256);
     g.off_pts = off;
-    off = align_up(off + g.pts.size() * sizeof(int32_t), 256);
+    off = align_up(off + std::max<size_t>(1, g.pts.size()) * sizeof(int32_t), 256);
     g.off_items = off;
     off = align_up(off + g.items.size() * sizeof(SpreadItem), 256);
     g.off_zero = off;
     off = align_up(off + std::max<size_t>(1, g.zero_tiles.size()) * sizeof(int32_t), 256);
   }
+  plan.off_desc = off;
+  off = align_up(off + size_t(ns) * sizeof(SliceDesc), 256);
+  plan.off_work = off;
+  off = align_up(off + std::max<size_t>(1, plan.work.size()) * sizeof(WorkItem), 256);
   plan.off_slot = off;
-  size_t t_bytes = 0, ext_bytes = 0, yh_bytes = 0;
-  for (const Geom& g : plan.geoms) {
-    t_bytes = std::max(t_bytes, size_t(g.G / 2 + 1) * g.key.n * sizeof(f2));
-    ext_bytes = std::max(ext_bytes, size_t(g.rows) * g.cols * sizeof(f2));
-    yh_bytes = std::max(yh_bytes, size_t(g.key.n_angles) * g.H * sizeof(f2));
-  }
-  plan.slot_t = 0;
-  plan.slot_ext = align_up(t_bytes, 256);
-  plan.slot_yh = align_up(plan.slot_ext + ext_bytes, 256);
-  plan.slot_bytes = align_up(plan.slot_yh + yh_bytes, 256);
-  plan.ws_bytes = plan.off_slot + plan.slot_bytes;
+  plan.ws_bytes = plan.off_slot + plan.slot_area;
+  plan.laid_out = true;
   return NR_OK;
+}
+
+std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
+  std::vector<SliceDesc> out(plan.slices.size());
+  for (const Batch& bt : plan.batches) {
+    for (size_t k = 0; k < bt.slices.size(); ++k) {
+      const int s = bt.slices[k];
+      const nr_slice& sl = plan.slices[size_t(s)];
+      const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
+      SliceDesc d{};
+      d.N = sl.n;
+      d.Nt = sl.n_det;
+      d.na = sl.n_angles;
+      d.G = g.G;
+      d.H = g.H;
+      d.rows = g.rows;
+      d.cols = g.cols;
+      d.tiles_x = g.tiles_x;
+      d.n_items = int(g.items.size());
+      d.n_zero = int(g.zero_tiles.size());
+      d.slot = int(k);
+      d.vol_off = sl.vol_off;
+      d.sino_off = sl.sino_off;
+      d.deapod = reinterpret_cast<const float*>(d_ws + plan.off_deapod.at(sl.n));
+      d.tw_G = reinterpret_cast<const float*>(d_ws + plan.off_twiddle.at(g.G));
+      d.tw_Nt = reinterpret_cast<const float*>(d_ws + plan.off_twiddle.at(sl.n_det));
+      d.gxy = reinterpret_cast<const double*>(d_ws + g.off_gxy);
+      d.flip = reinterpret_cast<const int32_t*>(d_ws + g.off_flip);
+      char* slot = d_ws + plan.off_slot + bt.slot_off[k];
+      const size_t ext_off = align_up(size_t(g.G / 2 + 1) * g.key.n * sizeof(f2), 256);
+      const size_t yh_off = align_up(ext_off + size_t(g.rows) * g.cols * sizeof(f2), 256);
+      d.T = reinterpret_cast<float*>(slot);
+      d.ext = reinterpret_cast<float*>(slot + ext_off);
+      d.yh = reinterpret_cast<float*>(slot + yh_off);
+      d.pts = reinterpret_cast<const int32_t*>(d_ws + g.off_pts);
+      d.items = reinterpret_cast<const SpreadItem*>(d_ws + g.off_items);
+      d.zero_tiles = reinterpret_cast<const int32_t*>(d_ws + g.off_zero);
+      out[size_t(s)] = d;
+    }
+  }
+  return out;
 }
 
 }  // namespace nr

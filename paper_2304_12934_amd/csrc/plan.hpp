@@ -1,6 +1,6 @@
 // Host-side plan: geometry validation, Kaiser-Bessel tables, per-angle
-// coordinate tables, spreading bins and the workspace layout.  Pure C++ (no
-// HIP) so it can be built and tested on a host without a GPU.
+// coordinate tables, spreading bins, batched work lists and the workspace
+// layout.  Pure C++ (no HIP) so it can be built and tested without a GPU.
 #pragma once
 
 #include <cstddef>
@@ -17,6 +17,9 @@ namespace nr {
 
 // FFT lengths compiled into the device library: 2^a (16..8192) and 5*2^a (80..5120).
 bool fft_length_supported(int L);
+
+// Spreading tile shapes compiled into the device library (width x height).
+bool spread_tile_supported(int w, int h);
 
 struct f2 {
   float x, y;
@@ -54,7 +57,6 @@ struct GeomKey {
   }
 };
 
-
 struct Geom {
   GeomKey key;
   int G = 0;            // oversampled grid size (sigma * N)
@@ -73,6 +75,35 @@ struct Geom {
   size_t off_gxy = 0, off_flip = 0, off_pts = 0, off_items = 0, off_zero = 0;
 };
 
+// Tunable execution parameters: none changes results beyond float32 rounding
+// (the order of the spreading sums).
+struct Tuning {
+  int tile_w = 64, tile_h = 32;   // spreading tile
+  int chunk = 1024;               // most points per spreading item
+  int batch = 0;                  // most slices per batched launch (0: no limit)
+  int batch_mb = 160;             // scratch budget of one batch in MiB (a lone slice may exceed it)
+  int spread_mode = 0;            // 0: LDS tiles, 1: global atomics (reference)
+};
+
+// Stages of the forward chain (FwdRows, FwdCols, FwdInterp) and of the
+// adjoint chain (AdjRadial, SpreadZero, Spread, AdjCols, AdjRows).
+enum class Stage : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero, Count };
+
+// One kernel launch of a batch: every unit of `stage` over the batch's
+// slices whose FFT length is L, listed at work_off in the workspace.
+struct StageLaunch {
+  Stage stage;
+  int L;
+  size_t work_off;    // bytes
+  int n_work;         // entries (XCD padding included)
+};
+
+struct Batch {
+  std::vector<int> slices;
+  std::vector<size_t> slot_off;   // scratch offset of each slice inside the slot area
+  std::vector<StageLaunch> fwd, adj;
+};
+
 struct Plan {
   std::vector<nr_slice> slices;
   std::vector<int> slice_geom;
@@ -80,28 +111,39 @@ struct Plan {
   std::vector<double> angles;       // copy of every referenced angle (indexed by angle_off + a)
   KaiserBessel kb;
   double sigma = 2.0;
-  int halo = 0;                     // (W-1)/2 rounded up: extra grid rows/cols each side
-  int colpad = 0;
+  int halo = 0;                     // grid rows beyond the half-plane on each side
+  int colpad = 0;                   // grid columns beyond the period on each side
 
   std::map<int, std::vector<float>> deapod;   // N -> 1/phihat((i - N/2)/G)
   std::map<int, size_t> off_deapod;
   std::map<int, std::vector<f2>> twiddle;     // L -> exp(-2 pi i m / L)
   std::map<int, size_t> off_twiddle;
 
-  size_t off_slot = 0;
-  size_t slot_t = 0, slot_ext = 0, slot_yh = 0;   // offsets inside the slot
-  size_t slot_bytes = 0;
+  Tuning tune;
+  bool laid_out = false;
+  std::vector<Batch> batches;
+  std::vector<WorkItem> work;       // every work list, concatenated
+  size_t off_desc = 0, off_work = 0, off_slot = 0;
+  size_t slot_area = 0;             // bytes of the largest batch's scratch
+  int n_slots = 0;                  // most slices in one batch
   size_t ws_bytes = 0;
 
   void* d_ws = nullptr;
   size_t d_ws_bytes = 0;
 };
 
-// Builds the plan; returns NR_OK or an error status with a message.
+// Geometry, kernel and FFT tables; returns NR_OK or an error status with a message.
 nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* angles,
                      const nr_nufft* params, Plan& plan, std::string& err);
 
-// Fills the spreading bins of one geometry (called by build_plan).
+// Spreading bins (for the current tuning), batches, work lists and the
+// workspace layout.  Idempotent until the tuning changes.
+nr_status layout_plan(Plan& plan, std::string& err);
+
+// Per-slice descriptors with absolute pointers into the workspace at d_ws.
+std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws);
+
+// Fills the spreading bins of one geometry (called by layout_plan).
 void build_spread_bins(const Plan& plan, Geom& g);
 
 }  // namespace nr

@@ -1,12 +1,12 @@
 // HIP kernels of the NUFFT Radon projector (forward chain F1-F4) and its
 // exact transpose (adjoint chain A1-A4) for gfx950.
 //
-// Data layout of one slice in the workspace (complex = float2):
+// Data layout of one slice in its workspace slot (complex = float2):
 //   T    [G/2+1][N]            row transform of the slice, stored transposed
 //                              (one contiguous column per kept frequency qx)
 //   ext  [rows][cols]          oversampled half-plane spectrum qx in [0, G/2]
 //                              plus `halo` rows on each side and `colpad`
-//                              columns on each side, so that every 7x7 (WxW)
+//                              columns on each side, so that every WxW
 //                              kernel footprint is a plain rectangle:
 //                                row r  <-> qx = r - halo
 //                                col p  <-> qy = p - colpad - G/2
@@ -29,9 +29,16 @@
 //   A3 k_adj_cols    fold halo cells back, inverse C2C along y, keep N rows
 //   A4 k_adj_rows    inverse half-spectrum transform along x for two rows,
 //                    deapodise, real output
+//
+// Every kernel is a grid-stride loop over a work list of (slice, unit)
+// items built by the plan, so one launch covers a batch of slices of mixed
+// sizes (one launch per FFT length); per-slice parameters come from a
+// device-resident SliceDesc.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 
 #include "fft.hpp"
 #include "radon_kernels.hpp"
@@ -39,8 +46,11 @@
 namespace nrk {
 
 // ---------------------------------------------------------------------------
-// Kaiser-Bessel tap weights
+// helpers
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float2* c2(float* p) { return reinterpret_cast<float2*>(p); }
+__device__ __forceinline__ const float2* c2(const float* p) { return reinterpret_cast<const float2*>(p); }
 
 // Coordinates of a polar point j on angle table entry (gx, gy): u = j*(gx, gy)
 // in grid cells, first tap g0 = ceil(u - W/2) and the W weights
@@ -77,45 +87,53 @@ __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
   return x < 0 ? x + L : (x >= L ? x - L : x);
 }
 
+// The loop every kernel runs: units of its work list, grid-stride.  Bodies
+// end with a barrier so the next unit may reuse the LDS.
+#define NR_FOR_EACH_UNIT(a, wi)                                \
+  for (int w_ = blockIdx.x; w_ < (a).n_work; w_ += gridDim.x) \
+    if (const WorkItem wi = (a).work[w_]; wi.slice >= 0)
+
 // ---------------------------------------------------------------------------
 // F1: rows (along x), two at a time, transposed store into T
 // ---------------------------------------------------------------------------
 
 template <int L>
-__global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(SliceArgs a) {
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(LaunchArgs a) {
   constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int N = a.N;
-  const int pair = xcd_block(N / 2);   // neighbouring row pairs share L2 lines of T
-  if (pair < 0) return;
-  const int iy0 = 2 * pair;
-  const float* __restrict__ f0 = a.vol_in + size_t(iy0) * N;
-  const float d0 = a.deapod[iy0], d1 = a.deapod[iy0 + 1];
-  // x = ix - N/2 sits at index x mod L
-  for (int n = tid; n < L; n += T) {
-    const int ix = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
-    float2 v = make_float2(0.f, 0.f);
-    if (ix >= 0) {
-      const float dx = a.deapod[ix];
-      v.x = dx * d0 * f0[ix];
-      v.y = dx * d1 * f0[N + ix];
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int N = d.N;
+    const int iy0 = 2 * wi.unit;
+    const float* __restrict__ f0 = a.vol_in + d.vol_off + size_t(iy0) * N;
+    const float d0 = d.deapod[iy0], d1 = d.deapod[iy0 + 1];
+    // x = ix - N/2 sits at index x mod L
+    for (int n = tid; n < L; n += T) {
+      const int ix = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
+      float2 v = make_float2(0.f, 0.f);
+      if (ix >= 0) {
+        const float dx = d.deapod[ix];
+        v.x = dx * d0 * f0[ix];
+        v.y = dx * d1 * f0[N + ix];
+      }
+      s[n] = v;
     }
-    s[n] = v;
-  }
-  __syncthreads();
-  fft_lds<L, T, false>(s, a.tw_G, tid);
-  // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
-  float4* __restrict__ out = reinterpret_cast<float4*>(a.T);
-  for (int q = tid; q <= L / 2; q += T) {
-    const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
-    float4 o;
-    o.x = 0.5f * (z1.x + z2.x);
-    o.y = 0.5f * (z1.y - z2.y);
-    o.z = 0.5f * (z1.y + z2.y);
-    o.w = 0.5f * (z2.x - z1.x);
-    out[(size_t(q) * N + iy0) >> 1] = o;
+    __syncthreads();
+    fft_lds<L, T, false>(s, c2(d.tw_G), tid);
+    // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
+    float4* __restrict__ out = reinterpret_cast<float4*>(d.T);
+    for (int q = tid; q <= L / 2; q += T) {
+      const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
+      float4 o;
+      o.x = 0.5f * (z1.x + z2.x);
+      o.y = 0.5f * (z1.y - z2.y);
+      o.z = 0.5f * (z1.y + z2.y);
+      o.w = 0.5f * (z2.x - z1.x);
+      out[(size_t(q) * N + iy0) >> 1] = o;
+    }
+    __syncthreads();
   }
 }
 
@@ -133,31 +151,36 @@ __device__ __forceinline__ void store_row(float2* row, int colpad, int n, float2
 }
 
 template <int L>
-__global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(SliceArgs a) {
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
   constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int N = a.N;
-  const int qx = blockIdx.x;
-  const float2* __restrict__ col = a.T + size_t(qx) * N;
-  for (int n = tid; n < L; n += T) {
-    const int iy = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
-    s[n] = iy >= 0 ? col[iy] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  fft_lds<L, T, false>(s, a.tw_G, tid);
-  const int halo = a.halo, colpad = a.colpad, cols = a.cols;
-  float2* row = a.ext + size_t(qx + halo) * cols;
-  // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
-  float2* m1 = (qx >= 1 && qx <= halo) ? a.ext + size_t(halo - qx) * cols : nullptr;
-  float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? a.ext + size_t(L - qx + halo) * cols : nullptr;
-  for (int n = tid; n < L; n += T) {
-    const float2 v = s[n];
-    store_row<L>(row, colpad, n, v);
-    const int nm = n == 0 ? 0 : L - n;
-    if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
-    if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+  const int halo = a.halo, colpad = a.colpad;
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int N = d.N, cols = d.cols;
+    const int qx = wi.unit;
+    const float2* __restrict__ col = c2(d.T) + size_t(qx) * N;
+    for (int n = tid; n < L; n += T) {
+      const int iy = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
+      s[n] = iy >= 0 ? col[iy] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<L, T, false>(s, c2(d.tw_G), tid);
+    float2* ext = c2(d.ext);
+    float2* row = ext + size_t(qx + halo) * cols;
+    // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
+    float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+    float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+    for (int n = tid; n < L; n += T) {
+      const float2 v = s[n];
+      store_row<L>(row, colpad, n, v);
+      const int nm = n == 0 ? 0 : L - n;
+      if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
+      if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+    }
+    __syncthreads();
   }
 }
 
@@ -166,11 +189,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(SliceArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int W>
-__device__ __forceinline__ float2 interp_point(const SliceArgs& a, const KBArgs& kb, int ang, int j) {
+__device__ __forceinline__ float2 interp_point(const SliceDesc& d, int halo, int colpad, const KBArgs& kb,
+                                               int ang, int j) {
   int g0x, g0y;
   float wx[W], wy[W];
-  point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
-  const float2* __restrict__ p = a.ext + size_t(g0x + a.halo) * a.cols + (g0y + a.G / 2 + a.colpad);
+  point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+  const float2* __restrict__ p = c2(d.ext) + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
   float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
   for (int i = 0; i < W; ++i) {
@@ -183,42 +207,52 @@ __device__ __forceinline__ float2 interp_point(const SliceArgs& a, const KBArgs&
     }
     acc.x = fmaf(wx[i], r.x, acc.x);
     acc.y = fmaf(wx[i], r.y, acc.y);
-    p += a.cols;
+    p += d.cols;
   }
-  if (a.flip[ang]) acc.y = -acc.y;
+  if (d.flip[ang]) acc.y = -acc.y;
   return acc;
 }
 
 template <int L, int W>
-__global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBArgs kb) {
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBArgs kb) {
   constexpr int T = fft_threads(L);
+  constexpr int H = L / 2 + 1;
   __shared__ float2 sbuf[lds_elems<L>()];
+  __shared__ float2 sy[H];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int pair = xcd_block((a.na + 1) / 2);   // neighbouring angles read the same grid lines
-  if (pair < 0) return;
-  const int a0 = 2 * pair, a1 = a0 + 1;
-  const bool has1 = a1 < a.na;
   const float inv = 1.0f / float(L);
-  // pack the Hermitian completions of both half-lines: Z = X + iY
-  for (int j = tid; j <= L / 2; j += T) {
-    float2 X = c_scale(interp_point<W>(a, kb, a0, j), inv);
-    float2 Y = has1 ? c_scale(interp_point<W>(a, kb, a1, j), inv) : make_float2(0.f, 0.f);
-    if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
-      X.y = 0.f;
-      Y.y = 0.f;
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int a0 = 2 * wi.unit, a1 = a0 + 1;
+    const bool has1 = a1 < d.na;
+    // the two half-lines, one point per iteration (X into s[0..H), Y into sy)
+    for (int p = tid; p < 2 * H; p += T) {
+      const int j = p < H ? p : p - H;
+      const int ang = p < H ? a0 : a1;
+      float2 v = make_float2(0.f, 0.f);
+      if (p < H || has1) v = c_scale(interp_point<W>(d, a.halo, a.colpad, kb, ang, j), inv);
+      if (j == 0 || j == L / 2) v.y = 0.f;   // the full line's sum is real: Re at k = 0 and k = -1/2
+      if (p < H) s[j] = v;
+      else sy[j] = v;
     }
-    s[j] = make_float2(X.x - Y.y, X.y + Y.x);
-    if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
-  }
-  __syncthreads();
-  fft_lds<L, T, true>(s, a.tw_Nt, tid);
-  // bin m (t = m - N_t/2) is output index t mod N_t
-  float* __restrict__ o0 = a.sino_out + size_t(a0) * L;
-  for (int m = tid; m < L; m += T) {
-    const float2 z = s[wrap_index<L>(m + L / 2)];
-    o0[m] = z.x;
-    if (has1) o0[L + m] = z.y;
+    __syncthreads();
+    // pack the Hermitian completions of both half-lines: Z = X + iY
+    for (int j = tid; j <= L / 2; j += T) {
+      const float2 X = s[j], Y = sy[j];
+      s[j] = make_float2(X.x - Y.y, X.y + Y.x);
+      if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
+    }
+    __syncthreads();
+    fft_lds<L, T, true>(s, c2(d.tw_Nt), tid);
+    // bin m (t = m - N_t/2) is output index t mod N_t
+    float* __restrict__ o0 = a.sino_out + d.sino_off + size_t(a0) * L;
+    for (int m = tid; m < L; m += T) {
+      const float2 z = s[wrap_index<L>(m + L / 2)];
+      o0[m] = z.x;
+      if (has1) o0[L + m] = z.y;
+    }
+    __syncthreads();
   }
 }
 
@@ -227,26 +261,30 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(SliceArgs a, KBAr
 // ---------------------------------------------------------------------------
 
 template <int L>
-__global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(SliceArgs a) {
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(LaunchArgs a) {
   constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int a0 = 2 * blockIdx.x, a1 = a0 + 1;
-  const bool has1 = a1 < a.na;
-  const float* __restrict__ y0 = a.sino_in + size_t(a0) * L;
-  for (int m = tid; m < L; m += T)
-    s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? y0[L + m] : 0.f);
-  __syncthreads();
-  fft_lds<L, T, false>(s, a.tw_Nt, tid);
-  const int H = L / 2 + 1;
-  float2* __restrict__ o0 = a.yh + size_t(a0) * H;
-  const float inv = 1.0f / float(L);
-  for (int j = tid; j < H; j += T) {
-    const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
-    const float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
-    o0[j] = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
-    if (has1) o0[H + j] = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int a0 = 2 * wi.unit, a1 = a0 + 1;
+    const bool has1 = a1 < d.na;
+    const float* __restrict__ y0 = a.sino_in + d.sino_off + size_t(a0) * L;
+    for (int m = tid; m < L; m += T)
+      s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? y0[L + m] : 0.f);
+    __syncthreads();
+    fft_lds<L, T, false>(s, c2(d.tw_Nt), tid);
+    const int H = L / 2 + 1;
+    float2* __restrict__ o0 = c2(d.yh) + size_t(a0) * H;
+    const float inv = 1.0f / float(L);
+    for (int j = tid; j < H; j += T) {
+      const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
+      const float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
+      o0[j] = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
+      if (has1) o0[H + j] = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+    }
+    __syncthreads();
   }
 }
 
@@ -260,12 +298,17 @@ __global__ void k_fill_zero(float4* p, size_t n4) {
 }
 
 // clear the tiles that several work items accumulate into
-__global__ __launch_bounds__(256) void k_spread_zero(SliceArgs a) {
-  const int t = a.zero_tiles[blockIdx.x];
-  const int r0 = (t / a.tiles_x) * a.tile_h, c0 = (t % a.tiles_x) * a.tile_w;
-  for (int c = threadIdx.x; c < a.tile_w * a.tile_h; c += blockDim.x) {
-    const int r = r0 + c / a.tile_w, cc = c0 + c % a.tile_w;
-    if (r < a.rows && cc < a.cols) a.ext[size_t(r) * a.cols + cc] = make_float2(0.f, 0.f);
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_spread_zero(LaunchArgs a) {
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int t = d.zero_tiles[wi.unit];
+    const int r0 = (t / d.tiles_x) * TH, c0 = (t % d.tiles_x) * TW;
+    float2* ext = c2(d.ext);
+    for (int c = threadIdx.x; c < TW * TH; c += 256) {
+      const int r = r0 + c / TW, cc = c0 + c % TW;
+      if (r < d.rows && cc < d.cols) ext[size_t(r) * d.cols + cc] = make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -276,141 +319,150 @@ __global__ __launch_bounds__(256) void k_spread_zero(SliceArgs a) {
 // M the largest |component| of its values and b the most of its points that
 // touch any one cell (from the plan), bounds every cell's final sum by 2^30
 // (|phi| <= 1), so the wrapped 32-bit partial sums are exact modulo 2^32 and
-// the final sum is exact up to the rounding of each contribution to 1/q.  Single-item tiles are then stored
-// plainly (every cell, zeros included); shared tiles are added with global
-// float atomics.
+// the final sum is exact up to the rounding of each contribution to 1/q.
+// Single-item tiles are then stored plainly (every cell, zeros included);
+// shared tiles are added with global float atomics.
 template <int W, int TW, int TH>
-__global__ __launch_bounds__(256) void k_spread_tiles(SliceArgs a, KBArgs kb) {
+__global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
   // row stride TW + 1: lanes stepping along a tile column hit different banks
   constexpr int TS = TW + 1;
   __shared__ int acc_re[TH * TS];
   __shared__ int acc_im[TH * TS];
   __shared__ float red[256];
-  const SpreadItem it = a.items[blockIdx.x];
+  __shared__ int nonfinite;
   const int tid = threadIdx.x;
-  for (int c = tid; c < TH * TS; c += 256) {
-    acc_re[c] = 0;
-    acc_im[c] = 0;
-  }
-  const int r0 = (it.tile / a.tiles_x) * TH, c0 = (it.tile % a.tiles_x) * TW;
-  const int rbase = a.halo - r0, cbase = a.G / 2 + a.colpad - c0;
-  // k = 0 of every angle sits at the origin: their sum is spread once
-  float dc = 0.f;
-  if (it.flags & 2) {
-    float sum = 0.f;
-    for (int ang = tid; ang < a.na; ang += 256) sum += a.yh[size_t(ang) * a.H].x;
-    red[tid] = sum;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const SpreadItem it = d.items[wi.unit];
+    const float2* __restrict__ yh = c2(d.yh);
+    for (int c = tid; c < TH * TS; c += 256) {
+      acc_re[c] = 0;
+      acc_im[c] = 0;
+    }
+    const int r0 = (it.tile / d.tiles_x) * TH, c0 = (it.tile % d.tiles_x) * TW;
+    const int rbase = a.halo - r0, cbase = d.G / 2 + a.colpad - c0;
+    // k = 0 of every angle sits at the origin: their sum is spread once
+    float dc = 0.f;
+    if (it.flags & kItemDC) {
+      float sum = 0.f;
+      for (int ang = tid; ang < d.na; ang += 256) sum += yh[size_t(ang) * d.H].x;
+      red[tid] = sum;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      dc = red[0];
       __syncthreads();
     }
-    dc = red[0];
+    // fixed-point scale of this item; a non-finite value (which the integer
+    // conversion would turn into 0) poisons the whole tile with NaN instead
+    if (tid == 0) nonfinite = !isfinite(dc);
+    float m = 0.f;
+    bool bad = false;
+    for (int e = it.begin + tid; e < it.end; e += 256) {
+      const float2 v = yh[d.pts[e]];
+      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+      bad |= !isfinite(v.x) || !isfinite(v.y);
+    }
+    red[tid] = m;
     __syncthreads();
-  }
-  // fixed-point scale of this item; a non-finite value (which the integer
-  // conversion would turn into 0) poisons the whole tile with NaN instead
-  __shared__ int nonfinite;
-  if (tid == 0) nonfinite = !isfinite(dc);
-  float m = 0.f;
-  bool bad = false;
-  for (int e = it.begin + tid; e < it.end; e += 256) {
-    const float2 v = a.yh[a.pts[e]];
-    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
-    bad |= !isfinite(v.x) || !isfinite(v.y);
-  }
-  red[tid] = m;
-  __syncthreads();
-  if (bad) nonfinite = 1;
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
-    __syncthreads();
-  }
-  const float mmax = fmaxf(red[0], fabsf(dc));
-  const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
-  if ((it.flags & 2) && tid < W * W) {
-    int g0x, g0y;
-    float wx[W], wy[W];
-    point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
-    const int i = tid / W, l = tid % W;
-    const int rr = g0x + i + rbase, cc = g0y + l + cbase;
-    if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(q * dc * wx[i] * wy[l]));
-  }
-  for (int e = it.begin + tid; e < it.end; e += 256) {
-    const int pid = a.pts[e];
-    const int ang = pid / a.H, j = pid - ang * a.H;
-    float2 v = a.yh[pid];
-    if (a.flip[ang]) v.y = -v.y;
-    v.x *= q;
-    v.y *= q;
-    int g0x, g0y;
-    float wx[W], wy[W];
-    point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
-    const int rr0 = g0x + rbase, cc0 = g0y + cbase;
-    if (rr0 >= 0 && rr0 + W <= TH && cc0 >= 0 && cc0 + W <= TW) {
-      // whole footprint inside the tile
-      int* pre = acc_re + rr0 * TS + cc0;
-      int* pim = acc_im + rr0 * TS + cc0;
+    if (bad) nonfinite = 1;
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    const float mmax = fmaxf(red[0], fabsf(dc));
+    const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
+    if ((it.flags & kItemDC) && tid < W * W) {
+      int g0x, g0y;
+      float wx[W], wy[W];
+      point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
+      const int i = tid / W, l = tid % W;
+      const int rr = g0x + i + rbase, cc = g0y + l + cbase;
+      if (rr >= 0 && rr < TH && cc >= 0 && cc < TW)
+        atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(q * dc * wx[i] * wy[l]));
+    }
+    for (int e = it.begin + tid; e < it.end; e += 256) {
+      const int pid = d.pts[e];
+      const int ang = pid / d.H, j = pid - ang * d.H;
+      float2 v = yh[pid];
+      if (d.flip[ang]) v.y = -v.y;
+      v.x *= q;
+      v.y *= q;
+      int g0x, g0y;
+      float wx[W], wy[W];
+      point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+      const int rr0 = g0x + rbase, cc0 = g0y + cbase;
+      if (rr0 >= 0 && rr0 + W <= TH && cc0 >= 0 && cc0 + W <= TW) {
+        // whole footprint inside the tile
+        int* pre = acc_re + rr0 * TS + cc0;
+        int* pim = acc_im + rr0 * TS + cc0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const float vx = wx[i] * v.x, vy = wx[i] * v.y;
+#pragma unroll
+          for (int l = 0; l < W; ++l) {
+            atomicAdd(pre + i * TS + l, __float2int_rn(vx * wy[l]));
+            atomicAdd(pim + i * TS + l, __float2int_rn(vy * wy[l]));
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int i = 0; i < W; ++i) {
+        const int rr = rr0 + i;
+        if (rr < 0 || rr >= TH) continue;
         const float vx = wx[i] * v.x, vy = wx[i] * v.y;
 #pragma unroll
         for (int l = 0; l < W; ++l) {
-          atomicAdd(pre + i * TS + l, __float2int_rn(vx * wy[l]));
-          atomicAdd(pim + i * TS + l, __float2int_rn(vy * wy[l]));
+          const int cc = cc0 + l;
+          if (cc < 0 || cc >= TW) continue;
+          atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(vx * wy[l]));
+          atomicAdd(&acc_im[rr * TS + cc], __float2int_rn(vy * wy[l]));
         }
       }
-      continue;
     }
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const int rr = rr0 + i;
-      if (rr < 0 || rr >= TH) continue;
-      const float vx = wx[i] * v.x, vy = wx[i] * v.y;
-#pragma unroll
-      for (int l = 0; l < W; ++l) {
-        const int cc = cc0 + l;
-        if (cc < 0 || cc >= TW) continue;
-        atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(vx * wy[l]));
-        atomicAdd(&acc_im[rr * TS + cc], __float2int_rn(vy * wy[l]));
+    __syncthreads();
+    const bool shared_tile = it.flags & kItemAtomic;
+    const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
+    float2* ext = c2(d.ext);
+    for (int c = tid; c < TH * TW; c += 256) {
+      const int rl = c / TW, cl = c % TW;
+      const int r = r0 + rl, cc = c0 + cl;
+      if (r >= d.rows || cc >= d.cols) continue;
+      float2* dst = ext + size_t(r) * d.cols + cc;
+      const float re = float(acc_re[rl * TS + cl]) * inv_q, im = float(acc_im[rl * TS + cl]) * inv_q;
+      if (shared_tile) {
+        atomicAdd(&dst->x, re);
+        atomicAdd(&dst->y, im);
+      } else {
+        *dst = make_float2(re, im);
       }
     }
-  }
-  __syncthreads();
-  const bool shared_tile = it.flags & 1;
-  const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
-  for (int c = tid; c < TH * TW; c += 256) {
-    const int rl = c / TW, cl = c % TW;
-    const int r = r0 + rl, cc = c0 + cl;
-    if (r >= a.rows || cc >= a.cols) continue;
-    float2* dst = a.ext + size_t(r) * a.cols + cc;
-    const float re = float(acc_re[rl * TS + cl]) * inv_q, im = float(acc_im[rl * TS + cl]) * inv_q;
-    if (shared_tile) {
-      atomicAdd(&dst->x, re);
-      atomicAdd(&dst->y, im);
-    } else {
-      *dst = make_float2(re, im);
-    }
+    __syncthreads();
   }
 }
 
-// Reference spreading: one thread per polar point, global float atomics
-// straight into the (cleared) extended grid.  Slow; used to cross-check.
+// Reference spreading: one thread per polar point of one slice, global float
+// atomics straight into the (cleared) extended grid.  Slow; a cross-check.
 template <int W>
-__global__ __launch_bounds__(256) void k_spread_atomic(SliceArgs a, KBArgs kb) {
+__global__ __launch_bounds__(256) void k_spread_atomic(const SliceDesc* descs, int slice, int halo, int colpad,
+                                                       KBArgs kb) {
+  const SliceDesc& d = descs[slice];
   const int pid = blockIdx.x * 256 + threadIdx.x;
-  if (pid >= a.na * a.H) return;
-  const int ang = pid / a.H, j = pid - ang * a.H;
-  float2 v = a.yh[pid];
-  if (a.flip[ang]) v.y = -v.y;
+  if (pid >= d.na * d.H) return;
+  const int ang = pid / d.H, j = pid - ang * d.H;
+  float2 v = c2(d.yh)[pid];
+  if (d.flip[ang]) v.y = -v.y;
   int g0x, g0y;
   float wx[W], wy[W];
-  point_taps<W>(a.gxy[2 * ang], a.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
-  float2* p = a.ext + size_t(g0x + a.halo) * a.cols + (g0y + a.G / 2 + a.colpad);
+  point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+  float2* p = c2(d.ext) + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
   for (int i = 0; i < W; ++i)
     for (int l = 0; l < W; ++l) {
-      atomicAdd(&p[size_t(i) * a.cols + l].x, wx[i] * wy[l] * v.x);
-      atomicAdd(&p[size_t(i) * a.cols + l].y, wx[i] * wy[l] * v.y);
+      atomicAdd(&p[size_t(i) * d.cols + l].x, wx[i] * wy[l] * v.x);
+      atomicAdd(&p[size_t(i) * d.cols + l].y, wx[i] * wy[l] * v.y);
     }
 }
 
@@ -429,27 +481,33 @@ __device__ __forceinline__ float2 load_folded(const float2* row, int colpad, int
 }
 
 template <int L>
-__global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(SliceArgs a) {
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
   constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int qx = blockIdx.x;
-  const int halo = a.halo, colpad = a.colpad, cols = a.cols, N = a.N;
-  const float2* row = a.ext + size_t(qx + halo) * cols;
-  const float2* m1 = (qx >= 1 && qx <= halo) ? a.ext + size_t(halo - qx) * cols : nullptr;
-  const float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? a.ext + size_t(L - qx + halo) * cols : nullptr;
-  for (int n = tid; n < L; n += T) {
-    float2 v = load_folded<L>(row, colpad, n);
-    const int nm = n == 0 ? 0 : L - n;
-    if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
-    if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
-    s[n] = v;
+  const int halo = a.halo, colpad = a.colpad;
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int qx = wi.unit;
+    const int cols = d.cols, N = d.N;
+    const float2* ext = c2(d.ext);
+    const float2* row = ext + size_t(qx + halo) * cols;
+    const float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+    const float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+    for (int n = tid; n < L; n += T) {
+      float2 v = load_folded<L>(row, colpad, n);
+      const int nm = n == 0 ? 0 : L - n;
+      if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+      if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+      s[n] = v;
+    }
+    __syncthreads();
+    fft_lds<L, T, true>(s, c2(d.tw_G), tid);
+    float2* __restrict__ out = c2(d.T) + size_t(qx) * N;
+    for (int iy = tid; iy < N; iy += T) out[iy] = s[wrap_index<L>(iy - N / 2)];
+    __syncthreads();
   }
-  __syncthreads();
-  fft_lds<L, T, true>(s, a.tw_G, tid);
-  float2* __restrict__ out = a.T + size_t(qx) * N;
-  for (int iy = tid; iy < N; iy += T) out[iy] = s[wrap_index<L>(iy - N / 2)];
 }
 
 // ---------------------------------------------------------------------------
@@ -457,36 +515,38 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(SliceArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int L>
-__global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
+__global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
   constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
-  const int N = a.N;
-  const int pair = xcd_block(N / 2);   // neighbouring row pairs share L2 lines of T
-  if (pair < 0) return;
-  const int iy0 = 2 * pair;
-  const float4* __restrict__ in = reinterpret_cast<const float4*>(a.T);
-  // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
-  for (int q = tid; q <= L / 2; q += T) {
-    const float4 t = in[(size_t(q) * N + iy0) >> 1];
-    float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
-    if (q == 0 || q == L / 2) {
-      X = make_float2(2.f * X.x, 0.f);
-      Y = make_float2(2.f * Y.x, 0.f);
+  NR_FOR_EACH_UNIT(a, wi) {
+    const SliceDesc& d = a.descs[wi.slice];
+    const int N = d.N;
+    const int iy0 = 2 * wi.unit;
+    const float4* __restrict__ in = reinterpret_cast<const float4*>(d.T);
+    // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
+    for (int q = tid; q <= L / 2; q += T) {
+      const float4 t = in[(size_t(q) * N + iy0) >> 1];
+      float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
+      if (q == 0 || q == L / 2) {
+        X = make_float2(2.f * X.x, 0.f);
+        Y = make_float2(2.f * Y.x, 0.f);
+      }
+      s[q] = make_float2(X.x - Y.y, X.y + Y.x);
+      if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
     }
-    s[q] = make_float2(X.x - Y.y, X.y + Y.x);
-    if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
-  }
-  __syncthreads();
-  fft_lds<L, T, true>(s, a.tw_G, tid);
-  const float d0 = 0.5f * a.deapod[iy0], d1 = 0.5f * a.deapod[iy0 + 1];
-  float* __restrict__ g0 = a.vol_out + size_t(iy0) * N;
-  for (int ix = tid; ix < N; ix += T) {
-    const float2 z = s[wrap_index<L>(ix - N / 2)];
-    const float dx = a.deapod[ix];
-    g0[ix] = dx * d0 * z.x;
-    g0[N + ix] = dx * d1 * z.y;
+    __syncthreads();
+    fft_lds<L, T, true>(s, c2(d.tw_G), tid);
+    const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
+    float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
+    for (int ix = tid; ix < N; ix += T) {
+      const float2 z = s[wrap_index<L>(ix - N / 2)];
+      const float dx = d.deapod[ix];
+      g0[ix] = dx * d0 * z.x;
+      g0[N + ix] = dx * d1 * z.y;
+    }
+    __syncthreads();
   }
 }
 
@@ -494,92 +554,131 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(SliceArgs a) {
 // launchers
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// resident workgroups of a kernel on the whole device (cached per kernel)
+int capacity(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 256, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int cap = cus * per_cu;
+  cache[kernel] = cap;
+  return cap;
+}
+
+// grid of a grid-stride launch over n work entries: all resident
+// workgroups, a multiple of the XCD count (so XCD-interleaved lists keep
+// their locality), never more than the list
+template <class K>
+int grid_for(K kernel, int threads, int n) {
+  const int cap = capacity(reinterpret_cast<const void*>(kernel), threads);
+  const int g = std::min(n, std::max(kXcds, cap / kXcds * kXcds));
+  return std::max(1, g);
+}
+
+template <class K, class... Args>
+hipError_t launch(K kernel, int threads, int n, hipStream_t st, Args... args) {
+  hipLaunchKernelGGL(kernel, dim3(grid_for(kernel, threads, n)), dim3(threads), 0, st, args...);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 #define NR_LENGTHS(X) \
   X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(80) X(160) X(320) X(640) X(1280) X(2560) X(5120)
 
-hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W, int spread_mode,
-                        hipStream_t st) {
-  const int G = a.G, Nt = a.Nt;
-  const int nb = (a.na + 1) / 2;
+template <int W>
+hipError_t launch_spread(const LaunchArgs& a, const KBArgs& kb, int tw, int th, hipStream_t st, bool zero) {
+#define NR_TILE(w, h)                                                               \
+  if (tw == w && th == h)                                                           \
+    return zero ? launch(k_spread_zero<w, h>, 256, a.n_work, st, a)                 \
+                : launch(k_spread_tiles<W, w, h>, 256, a.n_work, st, a, kb);
+  NR_TILE(64, 32)
+  NR_TILE(32, 32)
+  NR_TILE(64, 64)
+  NR_TILE(128, 32)
+#undef NR_TILE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArgs& kb, int W, int tile_w,
+                        int tile_h, hipStream_t st) {
+  if (a.n_work <= 0) return hipSuccess;
   switch (stage) {
-    case Stage::FwdRows:
-      switch (G) {
-#define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_fwd_rows<l>, dim3(xcd_grid(a.N / 2)), dim3(fft_threads(l)), 0, st, a); break;
+    case StageKind::FwdRows:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_fwd_rows<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
-    case Stage::FwdCols:
-      switch (G) {
-#define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_fwd_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); break;
+    case StageKind::FwdCols:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_fwd_cols<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
-    case Stage::FwdInterp:
-      switch (Nt) {
-#define NR_CASE(l)                                                                                          \
-  case l:                                                                                                   \
-    if (W == 6) hipLaunchKernelGGL((k_fwd_interp<l, 6>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb);     \
-    else if (W == 7) hipLaunchKernelGGL((k_fwd_interp<l, 7>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb); \
-    else hipLaunchKernelGGL((k_fwd_interp<l, 8>), dim3(xcd_grid(nb)), dim3(fft_threads(l)), 0, st, a, kb);             \
-    break;
+    case StageKind::FwdInterp:
+      switch (L) {
+#define NR_CASE(l)                                                                          \
+  case l:                                                                                   \
+    if (W == 6) return launch(k_fwd_interp<l, 6>, fft_threads(l), a.n_work, st, a, kb);     \
+    if (W == 7) return launch(k_fwd_interp<l, 7>, fft_threads(l), a.n_work, st, a, kb);     \
+    return launch(k_fwd_interp<l, 8>, fft_threads(l), a.n_work, st, a, kb);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
-    case Stage::AdjRadial:
-      switch (Nt) {
-#define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_adj_radial<l>, dim3(nb), dim3(fft_threads(l)), 0, st, a); break;
+    case StageKind::AdjRadial:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_adj_radial<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
-    case Stage::Spread:
-      if (spread_mode == 1) {
-        const size_t n4 = size_t(a.rows) * a.cols / 2;
-        hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(a.ext), n4);
-        const int np = a.na * a.H;
-        const dim3 g((np + 255) / 256);
-        if (W == 6) hipLaunchKernelGGL(k_spread_atomic<6>, g, dim3(256), 0, st, a, kb);
-        else if (W == 7) hipLaunchKernelGGL(k_spread_atomic<7>, g, dim3(256), 0, st, a, kb);
-        else hipLaunchKernelGGL(k_spread_atomic<8>, g, dim3(256), 0, st, a, kb);
-      } else {
-        if (a.tile_w != 64 || a.tile_h != 32) return hipErrorInvalidValue;
-        if (a.n_zero > 0) hipLaunchKernelGGL(k_spread_zero, dim3(a.n_zero), dim3(256), 0, st, a);
-        if (W == 6) hipLaunchKernelGGL((k_spread_tiles<6, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-        else if (W == 7) hipLaunchKernelGGL((k_spread_tiles<7, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-        else hipLaunchKernelGGL((k_spread_tiles<8, 64, 32>), dim3(a.n_items), dim3(256), 0, st, a, kb);
-      }
-      break;
-    case Stage::AdjCols:
-      switch (G) {
-#define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_adj_cols<l>, dim3(l / 2 + 1), dim3(fft_threads(l)), 0, st, a); break;
+    case StageKind::SpreadZero:
+    case StageKind::Spread: {
+      const bool zero = stage == StageKind::SpreadZero;
+      if (W == 6) return launch_spread<6>(a, kb, tile_w, tile_h, st, zero);
+      if (W == 7) return launch_spread<7>(a, kb, tile_w, tile_h, st, zero);
+      return launch_spread<8>(a, kb, tile_w, tile_h, st, zero);
+    }
+    case StageKind::AdjCols:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_adj_cols<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
-    case Stage::AdjRows:
-      switch (G) {
-#define NR_CASE(l) \
-  case l: hipLaunchKernelGGL(k_adj_rows<l>, dim3(xcd_grid(a.N / 2)), dim3(fft_threads(l)), 0, st, a); break;
+    case StageKind::AdjRows:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_adj_rows<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
-        default: return hipErrorInvalidValue;
       }
       break;
     default:
-      return hipErrorInvalidValue;
+      break;
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spread_reference(const SliceDesc* d_descs, int slice, const SliceDesc& host_desc, int halo,
+                                   int colpad, const KBArgs& kb, int W, hipStream_t st) {
+  const size_t n4 = size_t(host_desc.rows) * host_desc.cols / 2;
+  hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, st, reinterpret_cast<float4*>(host_desc.ext), n4);
+  const int np = host_desc.na * host_desc.H;
+  const dim3 g((np + 255) / 256);
+  if (W == 6) hipLaunchKernelGGL(k_spread_atomic<6>, g, dim3(256), 0, st, d_descs, slice, halo, colpad, kb);
+  else if (W == 7) hipLaunchKernelGGL(k_spread_atomic<7>, g, dim3(256), 0, st, d_descs, slice, halo, colpad, kb);
+  else hipLaunchKernelGGL(k_spread_atomic<8>, g, dim3(256), 0, st, d_descs, slice, halo, colpad, kb);
   return hipGetLastError();
 }
 

@@ -7,27 +7,16 @@
 
 namespace nrk {
 
-// Everything one slice's kernels need, by value.
-struct SliceArgs {
-  const float* vol_in;     // forward input  f[N][N]
-  float* vol_out;          // adjoint output g[N][N]
-  const float* sino_in;    // adjoint input  y[na][Nt]
-  float* sino_out;         // forward output s[na][Nt]
-  int N, Nt, na, G, H;
-  int rows, cols, halo, colpad;
-  const float* deapod;     // [N] 1/phihat((i - N/2)/G)
-  const float2* tw_G;      // [G] exp(-2 pi i m/G)
-  const float2* tw_Nt;     // [Nt] exp(-2 pi i m/Nt)
-  const double* gxy;       // [na][2] grid step per radial index
-  const int* flip;         // [na] conjugate flag
-  float2* T;               // [G/2+1][N]
-  float2* ext;             // [rows][cols]
-  float2* yh;              // [na][H]
-  const int* pts;          // spreading point lists
-  const SpreadItem* items;
-  const int* zero_tiles;
-  int n_items, n_zero;
-  int tile_w, tile_h, tiles_x;
+// Arguments of one stage launch (by value).
+struct LaunchArgs {
+  const SliceDesc* descs;   // device array, one per slice of the plan
+  const WorkItem* work;     // device work list of this launch
+  int n_work;
+  int halo, colpad;
+  const float* vol_in;      // caller buffers (+ per-slice offsets)
+  float* vol_out;
+  const float* sino_in;
+  float* sino_out;
 };
 
 // Kaiser-Bessel tap polynomials: c[i*(W+3) + k] is the z^k coefficient of tap i.
@@ -35,11 +24,17 @@ struct KBArgs {
   float c[8 * 11];
 };
 
-// Stages of the forward chain (FwdRows, FwdCols, FwdInterp) and of the
-// adjoint chain (AdjRadial, Spread, AdjCols, AdjRows), launched in that order.
-enum class Stage : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, Count };
+// The stage kernels (same order as nr::Stage).
+enum class StageKind : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero };
 
-// spread_mode 0: LDS tiles (default), 1: plain global atomics (reference)
-hipError_t launch_stage(Stage stage, const SliceArgs& a, const KBArgs& kb, int W, int spread_mode, hipStream_t st);
+// One grid-stride launch of `stage` over its work list; L = FFT length of the
+// slices in the list (unused by the spreading stages).
+hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArgs& kb, int W, int tile_w,
+                        int tile_h, hipStream_t st);
+
+// Reference spreading of one slice (clear + one thread per point with
+// global float atomics); host_desc is the host copy of that slice's descriptor.
+hipError_t launch_spread_reference(const SliceDesc* d_descs, int slice, const SliceDesc& host_desc, int halo,
+                                   int colpad, const KBArgs& kb, int W, hipStream_t st);
 
 }  // namespace nrk

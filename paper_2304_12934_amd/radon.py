@@ -58,7 +58,8 @@ class Plan:
     """
 
     def __init__(self, geoms: Sequence[SliceGeometry], width: int = 7, beta: float = 0.0,
-                 device: torch.device | str | None = None, share_angles: bool = True):
+                 device: torch.device | str | None = None, share_angles: bool = True,
+                 tuning: dict | None = None):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
             raise ValueError("the projector runs on a GPU device only")
@@ -92,17 +93,47 @@ class Plan:
                                self._angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(params), ctypes.byref(handle)), "nr_plan_create")
         self._h = handle
+        self.tuning = {}
+        self._ws = None
+        self.retune(**(tuning or {}))
+        u = self.geoms[0]
+        self.uniform = all(g.n == u.n and g.n_det == u.n_det and len(g.angles) == len(u.angles)
+                           for g in self.geoms)
+
+    def retune(self, **kw) -> None:
+        """Apply execution parameters (tile_w, tile_h, chunk, batch, spread_mode)
+        and (re)bind a workspace of the size the new layout needs."""
+        L = lib()
+        for k, v in kw.items():
+            check(L.nr_plan_tune(self._h, k.encode(), int(v)), f"nr_plan_tune({k})")
+            self.tuning[k] = int(v)
+        if self._ws is not None and set(kw) <= {"spread_mode"}:
+            return
         nbytes = ctypes.c_size_t()
         check(L.nr_plan_workspace_bytes(self._h, ctypes.byref(nbytes)), "nr_plan_workspace_bytes")
         self.workspace_bytes = int(nbytes.value)
+        self._ws = None
         self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws.data_ptr()) % 256
         ws_ptr = ctypes.c_void_p(self._ws.data_ptr() + off)
         with torch.cuda.device(self.device):
             check(L.nr_plan_bind(self._h, ws_ptr, self.workspace_bytes, _stream(self.device)), "nr_plan_bind")
-        u = self.geoms[0]
-        self.uniform = all(g.n == u.n and g.n_det == u.n_det and len(g.angles) == len(u.angles)
-                           for g in self.geoms)
+
+    def capture(self, what: str, vol_in: torch.Tensor | None = None, sino: torch.Tensor | None = None,
+                vol_out: torch.Tensor | None = None) -> "Graph":
+        """Capture 'fwd', 'adj' or 'fwd+adj' over these buffers into one HIP graph."""
+        code = {"fwd": 1, "adj": 2, "fwd+adj": 3}[what]
+        if code & 1:
+            _require(vol_in, self.vol_numel, self.device, "vol_in")
+        _require(sino, self.sino_numel, self.device, "sino")
+        if code & 2:
+            _require(vol_out, self.vol_numel, self.device, "vol_out")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().nr_graph_capture_radon(self._h, code, _ptr(vol_in) if code & 1 else None, _ptr(sino),
+                                               _ptr(vol_out) if code & 2 else None, ctypes.byref(h)),
+                  "nr_graph_capture_radon")
+        return Graph(h, self, (vol_in, sino, vol_out))
 
     @classmethod
     def uniform_stack(cls, n: int, n_det: int, angles, n_slices: int = 1, **kw) -> "Plan":
@@ -163,15 +194,36 @@ class Plan:
         check(lib().nr_plan_tune(self._h, key.encode(), int(value)), "nr_plan_tune")
 
     def info(self, index: int = 0) -> dict:
-        buf = (ctypes.c_int64 * 5)()
-        check(lib().nr_plan_info(self._h, index, buf, 5), "nr_plan_info")
-        return {"G": buf[0], "tiles": buf[1], "tile_entries": buf[2], "spread_items": buf[3], "poly_degree": buf[4]}
+        buf = (ctypes.c_int64 * 8)()
+        check(lib().nr_plan_info(self._h, index, buf, 8), "nr_plan_info")
+        keys = ("G", "tiles", "tile_entries", "spread_items", "poly_degree", "slots", "batches", "launches")
+        return dict(zip(keys, list(buf)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             try:
                 lib().nr_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class Graph:
+    """A captured HIP graph (keeps its plan and buffers alive)."""
+
+    def __init__(self, handle: ctypes.c_void_p, plan: Plan, keep: tuple):
+        self._h, self.plan, self._keep = handle, plan, keep
+
+    def launch(self) -> None:
+        with torch.cuda.device(self.plan.device):
+            check(lib().nr_graph_launch(self._h, _stream(self.plan.device)), "nr_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().nr_graph_destroy(h)
             except Exception:
                 pass
             self._h = None
@@ -320,6 +372,16 @@ class MBIR:
         for _ in range(iters):
             self.step()
         return self.x
+
+    def capture(self, iters: int = 1) -> Graph:
+        """Capture `iters` consecutive mbir_step calls on this state into one HIP graph."""
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.plan.device):
+            check(lib().nr_graph_capture_mbir(self.plan._h, ctypes.byref(self._prior_c), ctypes.byref(self.params),
+                                              _ptr(self.b), _ptr(self.x), _ptr(self.x_prev), _ptr(self.y),
+                                              _ptr(self.grad), _ptr(self.scratch), _ptr(self.state), int(iters),
+                                              ctypes.byref(h)), "nr_graph_capture_mbir")
+        return Graph(h, self.plan, (self.b, self.x, self.x_prev, self.y, self.grad, self.scratch, self.state))
 
     def step_autograd(self) -> None:
         """Same iteration with the gradient from autograd: ``DataFidelityFn``

@@ -1,0 +1,139 @@
+"""Batched uneven stacks, tuned execution shapes and HIP-graph replays (through the C ABI)."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import radon as ora
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import paper_2304_12934_amd._lib as L
+    L.lib()
+    return torch.device("cuda", 0)
+
+
+def uneven_geoms(seed=60, count=12):
+    """Sizes from {64, 128, 256}, angle counts in [20, 200], sparse or limited view."""
+    from paper_2304_12934_amd import SliceGeometry
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([64, 128, 256]))
+        na = int(rng.integers(20, 201))
+        ang = synth.sparse_angles(rng, na) if i % 2 == 0 else synth.limited_view_angles(rng, na)
+        out.append(SliceGeometry(n, n, ang))
+    return out
+
+
+def test_batched_equals_per_slice_and_oracle(dev):
+    from paper_2304_12934_amd import Plan
+    say("case: uneven stack of 12, batch 12 vs batch 1")
+    geoms = uneven_geoms()
+    rng = np.random.default_rng(61)
+    one = Plan(geoms, device=dev, tuning={"batch": 1})
+    all_ = Plan(geoms, device=dev, tuning={"batch": len(geoms)})
+    assert all_.info()["batches"] == 1 and one.info()["batches"] == len(geoms)
+    x = torch.as_tensor(rng.standard_normal(one.vol_numel), dtype=torch.float32, device=dev)
+    y = torch.as_tensor(rng.standard_normal(one.sino_numel), dtype=torch.float32, device=dev)
+    s1, s2 = one.fwd(x), all_.fwd(x)
+    assert torch.equal(s1, s2)                       # the forward does not depend on batching
+    g1, g2 = one.adj(y), all_.adj(y)
+    assert rel(g2.cpu().numpy(), g1.cpu().numpy()) < 1e-6
+    xs, ys = x.cpu().numpy(), y.cpu().numpy()
+    for i in (0, 5, 11):
+        g = geoms[i]
+        vo, so = one.vol_offsets[i], one.sino_offsets[i]
+        f = xs[vo:vo + g.n * g.n].reshape(g.n, g.n)
+        yy = ys[so:so + len(g.angles) * g.n_det].reshape(len(g.angles), g.n_det)
+        assert rel(s2.cpu().numpy()[so:so + yy.size], ora.radon_fwd(f, g.angles, g.n_det)) < 1e-5
+        assert rel(g2.cpu().numpy()[vo:vo + f.size], ora.radon_adj(yy, g.angles, g.n)) < 1e-5
+
+
+@pytest.mark.parametrize("tw,th,chunk", [(32, 32, 1024), (64, 64, 512), (128, 32, 2048), (64, 32, 256)])
+def test_tuned_shapes_change_results_only_by_rounding(dev, tw, th, chunk):
+    from paper_2304_12934_amd import Plan
+    say(f"case: spread tile {tw}x{th}, chunk {chunk}")
+    rng = np.random.default_rng(62)
+    ang = rng.uniform(0, np.pi, 150)
+    ref = Plan.uniform_stack(256, 256, ang, 2, device=dev)
+    tuned = Plan.uniform_stack(256, 256, ang, 2, device=dev, tuning={"tile_w": tw, "tile_h": th, "chunk": chunk})
+    y = torch.as_tensor(rng.standard_normal((2, 150, 256)), dtype=torch.float32, device=dev)
+    assert rel(tuned.adj(y).cpu().numpy(), ref.adj(y).cpu().numpy()) < 1e-6
+
+
+def test_graph_replays_match_eager(dev):
+    from paper_2304_12934_amd import Plan
+    say("case: graph fwd+adj, 3 replays with eager work between")
+    geoms = uneven_geoms(63, 8)
+    plan = Plan(geoms, device=dev)
+    rng = np.random.default_rng(64)
+    x = torch.as_tensor(rng.standard_normal(plan.vol_numel), dtype=torch.float32, device=dev)
+    sino = torch.empty(plan.sino_numel, dtype=torch.float32, device=dev)
+    back = torch.empty(plan.vol_numel, dtype=torch.float32, device=dev)
+    graph = plan.capture("fwd+adj", x, sino, back)
+    for k in range(3):
+        # eager work on the same buffers between replays
+        x.mul_(1.0 + 0.1 * k)
+        s_ref = plan.fwd(x).clone()
+        g_ref = plan.adj(s_ref).clone()
+        torch.cuda.synchronize()
+        sino.zero_()
+        back.zero_()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(sino, s_ref), k
+        assert rel(back.cpu().numpy(), g_ref.cpu().numpy()) < 1e-6, k
+
+
+def test_mbir_graph_matches_eager_steps(dev):
+    from paper_2304_12934_amd import MBIR, Plan, Prior, power_lipschitz
+    say("case: MBIR graph of 3 steps vs eager steps")
+    rng = np.random.default_rng(65)
+    n, nz = 64, 4
+    vol = synth.rasterize_ellipsoids(synth.ellipsoid_params(rng, n, nz, 5), n, nz).numpy()
+    plan = Plan.uniform_stack(n, n, synth.uniform_angles(60), nz, device=dev)
+    b = plan.fwd(torch.as_tensor(vol, dtype=torch.float32, device=dev))
+    prior = Prior(lam=0.1, c=0.01, sigma=1.0)
+    L = power_lipschitz(plan, 30) + prior.lipschitz()
+    eager = MBIR(plan, b, prior, L)
+    graphed = MBIR(plan, b, prior, L)
+    g = graphed.capture(3)
+    for rep in range(2):
+        for _ in range(3):
+            eager.step()
+        g.launch()
+        torch.cuda.synchronize()
+        assert rel(graphed.x.cpu().numpy(), eager.x.cpu().numpy()) < 1e-5, rep
+        assert abs(float(graphed.state[0]) - float(eager.state[0])) < 1e-12
+
+
+def test_tuning_errors(dev):
+    from paper_2304_12934_amd import Plan
+    from paper_2304_12934_amd._lib import NrError
+    say("case: tuning errors")
+    plan = Plan.uniform_stack(64, 64, synth.uniform_angles(16), 1, device=dev)
+    with pytest.raises(NrError):
+        plan.retune(tile_w=48)
+    with pytest.raises(NrError):
+        plan.retune(chunk=8)
+    plan.retune(tile_w=64, chunk=1024)
+    x = torch.zeros((1, 64, 64), dtype=torch.float32, device=dev)
+    assert plan.fwd(x).abs().max().item() == 0.0

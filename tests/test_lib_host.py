@@ -104,14 +104,27 @@ def test_plan_info_and_workspace(L):
     ang = np.linspace(0, np.pi, 90, endpoint=False)
     st, h = _create(L, [(128, 128, 90, 0, 0, 0), (128, 128, 90, 128 * 128, 90 * 128, 0)], ang)
     assert st == _lib.NR_OK
-    info = (ctypes.c_int64 * 5)()
-    assert L.nr_plan_info(h, 1, info, 5) == _lib.NR_OK
-    G, tiles, entries, items, degree = list(info)
+    info = (ctypes.c_int64 * 8)()
+    assert L.nr_plan_info(h, 1, info, 8) == _lib.NR_OK
+    G, tiles, entries, items, degree, slots, batches, launches = list(info)
     assert G == 256 and degree == 9
+    assert slots == 2 and batches == 1          # both small slices share one batch
+    assert launches == 3 + 5                     # forward 3, adjoint 4 + the tile clear
     assert entries >= 90 * 64          # every point j >= 1 sits in at least one tile
     assert items >= tiles
     nbytes = ctypes.c_size_t()
     assert L.nr_plan_workspace_bytes(h, ctypes.byref(nbytes)) == _lib.NR_OK
     # at least the extended half-plane grid (G/2 + 1 + 8 rows of G + 8 complex)
     assert nbytes.value >= (G // 2 + 9) * (G + 8) * 8
+    # tuning: one slice per batch halves the scratch, an unknown tile is refused
+    assert L.nr_plan_tune(h, b"batch", 1) == _lib.NR_OK
+    small = ctypes.c_size_t()
+    assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_OK
+    assert small.value < nbytes.value
+    assert L.nr_plan_info(h, 0, info, 8) == _lib.NR_OK and info[5] == 1 and info[6] == 2
+    assert L.nr_plan_tune(h, b"tile_w", 48) == _lib.NR_OK
+    assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_UNSUPPORTED_SIZE
+    assert L.nr_plan_tune(h, b"tile_w", 32) == _lib.NR_OK
+    assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_OK
+    assert L.nr_plan_tune(h, b"no_such_key", 1) == _lib.NR_INVALID_ARG
     L.nr_plan_destroy(h)
