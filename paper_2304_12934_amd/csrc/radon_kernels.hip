@@ -30,15 +30,13 @@
 //   A4 k_adj_rows    inverse half-spectrum transform along x for two rows,
 //                    deapodise, real output
 //
-// Every kernel is a grid-stride loop over a work list of (slice, unit)
-// items built by the plan, so one launch covers a batch of slices of mixed
-// sizes (one launch per FFT length); per-slice parameters come from a
-// device-resident SliceDesc.
+// Every kernel takes its unit from a work list of (slice, unit) items built
+// by the plan, so one launch covers a batch of slices of mixed sizes (one
+// launch per FFT length); per-slice parameters come from a device-resident
+// SliceDesc.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <mutex>
-#include <unordered_map>
 
 #include "fft.hpp"
 #include "radon_kernels.hpp"
@@ -87,11 +85,11 @@ __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
   return x < 0 ? x + L : (x >= L ? x - L : x);
 }
 
-// The loop every kernel runs: units of its work list, grid-stride.  Bodies
-// end with a barrier so the next unit may reuse the LDS.
-#define NR_FOR_EACH_UNIT(a, wi)                                \
-  for (int w_ = blockIdx.x; w_ < (a).n_work; w_ += gridDim.x) \
-    if (const WorkItem wi = (a).work[w_]; wi.slice >= 0)
+// Every kernel runs one unit of its work list per workgroup (block b takes
+// entry b); padding entries (slice < 0) and blocks past the list do nothing.
+#define NR_FOR_EACH_UNIT(a, wi)                                                                    \
+  if (const WorkItem wi = int(blockIdx.x) < (a).n_work ? (a).work[blockIdx.x] : WorkItem{-1, 0}; \
+      wi.slice >= 0)
 
 // ---------------------------------------------------------------------------
 // F1: rows (along x), two at a time, transposed store into T
@@ -216,9 +214,7 @@ __device__ __forceinline__ float2 interp_point(const SliceDesc& d, int halo, int
 template <int L, int W>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBArgs kb) {
   constexpr int T = fft_threads(L);
-  constexpr int H = L / 2 + 1;
   __shared__ float2 sbuf[lds_elems<L>()];
-  __shared__ float2 sy[H];
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   const float inv = 1.0f / float(L);
@@ -226,20 +222,15 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
     const SliceDesc& d = a.descs[wi.slice];
     const int a0 = 2 * wi.unit, a1 = a0 + 1;
     const bool has1 = a1 < d.na;
-    // the two half-lines, one point per iteration (X into s[0..H), Y into sy)
-    for (int p = tid; p < 2 * H; p += T) {
-      const int j = p < H ? p : p - H;
-      const int ang = p < H ? a0 : a1;
-      float2 v = make_float2(0.f, 0.f);
-      if (p < H || has1) v = c_scale(interp_point<W>(d, a.halo, a.colpad, kb, ang, j), inv);
-      if (j == 0 || j == L / 2) v.y = 0.f;   // the full line's sum is real: Re at k = 0 and k = -1/2
-      if (p < H) s[j] = v;
-      else sy[j] = v;
-    }
-    __syncthreads();
-    // pack the Hermitian completions of both half-lines: Z = X + iY
+    // both half-lines per iteration (two independent gathers in flight), packed
+    // as the Hermitian completions Z = X + iY
     for (int j = tid; j <= L / 2; j += T) {
-      const float2 X = s[j], Y = sy[j];
+      float2 X = c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a0, j), inv);
+      float2 Y = has1 ? c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a1, j), inv) : make_float2(0.f, 0.f);
+      if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
+        X.y = 0.f;
+        Y.y = 0.f;
+      }
       s[j] = make_float2(X.x - Y.y, X.y + Y.x);
       if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
     }
@@ -556,30 +547,15 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
 
 namespace {
 
-// resident workgroups of a kernel on the whole device (cached per kernel)
-int capacity(const void* kernel, int threads) {
-  static std::mutex mu;
-  static std::unordered_map<const void*, int> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(kernel);
-  if (it != cache.end()) return it->second;
-  int dev = 0, cus = 256, per_cu = 1;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  const int cap = cus * per_cu;
-  cache[kernel] = cap;
-  return cap;
-}
-
-// grid of a grid-stride launch over n work entries: all resident
-// workgroups, a multiple of the XCD count (so XCD-interleaved lists keep
-// their locality), never more than the list
+// grid of a launch over n work entries: one workgroup per entry, so the
+// hardware dispatcher balances uneven units (a grid capped at the resident
+// capacity, striding statically over the list, measured slower on the
+// spreading and column stages)
 template <class K>
 int grid_for(K kernel, int threads, int n) {
-  const int cap = capacity(reinterpret_cast<const void*>(kernel), threads);
-  const int g = std::min(n, std::max(kXcds, cap / kXcds * kXcds));
-  return std::max(1, g);
+  (void)kernel;
+  (void)threads;
+  return std::max(1, n);
 }
 
 template <class K, class... Args>

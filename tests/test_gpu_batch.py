@@ -137,3 +137,21 @@ def test_tuning_errors(dev):
     plan.retune(tile_w=64, chunk=1024)
     x = torch.zeros((1, 64, 64), dtype=torch.float32, device=dev)
     assert plan.fwd(x).abs().max().item() == 0.0
+
+
+def test_autotuner_picks_a_setting_and_caches_it(dev, tmp_path):
+    from paper_2304_12934_amd import Plan
+    from paper_2304_12934_amd.autotune import autotune
+    say("case: autotuner on an uneven stack of 6")
+    geoms = uneven_geoms(66, 6)
+    cache = str(tmp_path / "tune.json")
+    best = autotune(geoms, device=dev, reps=1, cache_path=cache)
+    assert set(best) >= {"tile_w", "tile_h", "chunk", "batch_mb"}
+    assert autotune(geoms, device=dev, reps=1, cache_path=cache) == best      # served from the cache
+    rng = np.random.default_rng(67)
+    ref = Plan(geoms, device=dev)
+    tuned = Plan(geoms, device=dev, tuning=best)
+    y = torch.as_tensor(rng.standard_normal(ref.sino_numel), dtype=torch.float32, device=dev)
+    x = torch.as_tensor(rng.standard_normal(ref.vol_numel), dtype=torch.float32, device=dev)
+    assert torch.equal(tuned.fwd(x), ref.fwd(x))
+    assert rel(tuned.adj(y).cpu().numpy(), ref.adj(y).cpu().numpy()) < 1e-6
