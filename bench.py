@@ -36,7 +36,8 @@ def stage_bytes(n: int, nd: int, na: int, tile_entries: int) -> dict:
     Each pass reads and writes its operands once at storage precision, with
     the half-plane grid of G(G/2+1) complex64 values (G = 2N) and H = N_t/2+1
     points per half-line.  The interpolation reads the inscribed disc of the
-    grid (pi/4 of it).  The spreading also reads its 4-byte point list.
+    grid (pi/4 of it), writes the half-line values and reads them back for
+    the radial transforms.  The spreading also reads its 4-byte point list.
     """
     G = 2 * n
     H = nd // 2 + 1
@@ -44,12 +45,53 @@ def stage_bytes(n: int, nd: int, na: int, tile_entries: int) -> dict:
     return {
         "fwd_rows": 4 * n * n + 8 * n * half,
         "fwd_cols": 8 * n * half + 8 * G * half,
-        "fwd_interp": 8 * G * half * math.pi / 4 + 4 * na * nd,
+        "fwd_interp": 8 * G * half * math.pi / 4 + 16 * na * H + 4 * na * nd,
         "adj_radial": 4 * na * nd + 8 * na * H,
         "spread": 8 * na * H + 4 * tile_entries + 8 * G * half,
         "adj_cols": 8 * G * half + 8 * n * half,
         "adj_rows": 8 * n * half + 4 * n * n,
     }
+
+
+KERNEL_SOURCES = ("radon_kernels.hip", "radon_kernels.hpp", "fft.hpp", "layout.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_radon_2560x1024.md")
+
+
+def kernel_source_digest() -> str:
+    """sha1 of the projector's kernel sources (the counters are stale once it changes)."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_12934_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str, n: int, na: int) -> float | None:
+    """HBM bytes of one launch of `stage` from the committed counter summary.
+
+    The summary holds FETCH_SIZE and WRITE_SIZE per dispatch (rocprofv3
+    --pmc), each scaled by what the same counter reads for a device copy of
+    known size, for one workload and one version of the kernel sources; None
+    when the workload or the sources differ.
+    """
+    if (n, na) != (2560, 1024) or not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, rows = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("source digest:"):
+                digest = line.split(":", 1)[1].strip().strip("`")
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 5 and cells[0] in ("fwd_rows", "fwd_cols", "fwd_interp", "adj_radial", "spread",
+                                                "adj_cols", "adj_rows"):
+                try:
+                    rows[cells[0]] = float(cells[4])
+                except ValueError:
+                    pass
+    if digest != kernel_source_digest():
+        return None
+    return rows.get(stage)
 
 
 def model_bytes_per_slice(n: int, nd: int, na: int) -> float:
@@ -289,11 +331,14 @@ def main() -> int:
     roofline = None
     if stages:
         dom = max((k for k in stages if k in sb), key=lambda k: stages[k][0])
-        per_ms = stages[dom][0] / stages[dom][1]
+        # one stage launch covers one batch (the spreading stage is two kernels: clear + spread)
+        per_ms = stages[dom][0] / (args.steps * max(1, info["batches"]))
         bytes_launch = sb[dom] * per_launch_slices
         achieved = bytes_launch / (per_ms * 1e-3) / 1e9
+        tb = measured_traffic(dom, n, na)
+        traffic = int(tb * per_launch_slices) if tb is not None else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "bytes_per_launch": int(bytes_launch), "ms_per_launch": round(per_ms, 5),
                     "slices_per_launch": per_launch_slices}
 

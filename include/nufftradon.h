@@ -110,7 +110,13 @@ nr_status nr_plan_destroy(nr_plan* plan);
 /* Set an execution parameter of a plan; none changes results beyond float32
  * rounding of the spreading sums.  Keys:
  *   "tile_w", "tile_h"  spreading tile (64x32 default; 32x32, 64x64, 128x32)
- *   "chunk"             most points per spreading work item (1024 default)
+ *   "chunk"             most points per spreading or interpolation work item
+ *                       (1024 default)
+ *   "interp_mode"       0 = interpolation from LDS-staged grid tiles (every
+ *                       point once, by the tile of its first tap) followed by
+ *                       the radial transforms (default); 1 = one pass per
+ *                       angle pair gathering straight from the grid (same
+ *                       sums in the same order)
  *   "batch"             most slices per batch (0: no limit): each stage kernel
  *                       runs once per batch (and FFT length) over all its
  *                       slices; the workspace holds the scratch of the

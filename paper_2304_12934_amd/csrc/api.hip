@@ -115,7 +115,8 @@ int stage_event_id(nr::Stage s) {
   switch (s) {
     case nr::Stage::FwdRows: return kStageFwdRows;
     case nr::Stage::FwdCols: return kStageFwdCols;
-    case nr::Stage::FwdInterp: return kStageFwdInterp;
+    case nr::Stage::FwdInterp:
+    case nr::Stage::FwdRadial: return kStageFwdInterp;
     case nr::Stage::AdjRadial: return kStageAdjRadial;
     case nr::Stage::SpreadZero:
     case nr::Stage::Spread: return kStageSpread;
@@ -303,6 +304,8 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
     if ((e = up(g.off_pts, g.pts.data(), g.pts.size() * sizeof(int32_t)))) break;
     if ((e = up(g.off_items, g.items.data(), g.items.size() * sizeof(SpreadItem)))) break;
     if ((e = up(g.off_zero, g.zero_tiles.data(), g.zero_tiles.size() * sizeof(int32_t)))) break;
+    if ((e = up(g.off_ipts, g.ipts.data(), g.ipts.size() * sizeof(int32_t)))) break;
+    if ((e = up(g.off_iitems, g.iitems.data(), g.iitems.size() * sizeof(SpreadItem)))) break;
   }
   if (!e) e = up(p.off_desc, plan->host_descs.data(), plan->host_descs.size() * sizeof(SliceDesc));
   if (!e) e = up(p.off_work, p.work.data(), p.work.size() * sizeof(WorkItem));
@@ -333,6 +336,9 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
     t.tile_h = int(value);
   } else if (std::strcmp(key, "chunk") == 0) {
     t.chunk = int(value);
+  } else if (std::strcmp(key, "interp_mode") == 0) {
+    if (value != 0 && value != 1) return fail(NR_INVALID_ARG, "interp_mode must be 0 (tiles) or 1 (direct)");
+    t.interp_mode = int(value);
   } else if (std::strcmp(key, "batch") == 0) {
     if (value < 0) return fail(NR_INVALID_ARG, "batch must be >= 0");
     t.batch = int(value);

@@ -12,6 +12,15 @@
 
 #include <hip/hip_runtime.h>
 
+// Buffers in global memory are typed as such in device code, which keeps
+// their loads and stores off the flat path (the host pass sees plain pointers).
+#ifdef __HIP_DEVICE_COMPILE__
+#define NR_G __attribute__((address_space(1)))
+#else
+#define NR_G
+#endif
+using TwPtr = const NR_G float2*;
+
 namespace nrk {
 
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -198,12 +207,24 @@ constexpr int kXcds = 8;
 // ---------------------------------------------------------------------------
 
 template <int L, int T, int P, bool INV>
-__device__ __forceinline__ void fft_pass(Lds s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) {
   constexpr int R = radix_of(L, P);
   constexpr int Ns = span_before(L, P);
   constexpr int NB = L / R;
   constexpr int PER = (NB + T - 1) / T;
   float2 v[PER][R];
+  float2 w[PER][R - 1];
+  // twiddles first (clamped index, no branch): their global loads overlap the
+  // LDS reads and the barrier
+  if constexpr (Ns > 1) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int j = (NB % T == 0 || tid + i * T < NB) ? tid + i * T : 0;
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[i][r - 1] = tw[r * k * (L / (Ns * R))];
+    }
+  }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = tid + i * T;
@@ -218,13 +239,9 @@ __device__ __forceinline__ void fft_pass(Lds s, const float2* __restrict__ tw, i
     const int j = tid + i * T;
     if (NB % T == 0 || j < NB) {
       const int k = j % Ns;
-      if (Ns > 1) {
+      if constexpr (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * (L / (Ns * R))];
-          if (INV) w.y = -w.y;
-          v[i][r] = c_mul(v[i][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[i][r] = c_mul(v[i][r], INV ? c_conj(w[i][r - 1]) : w[i][r - 1]);
       }
       Dft<R, INV>::run(v[i]);
       const int base = (j - k) * R + k;
@@ -236,7 +253,7 @@ __device__ __forceinline__ void fft_pass(Lds s, const float2* __restrict__ tw, i
 }
 
 template <int L, int T, bool INV, int P = 0>
-__device__ __forceinline__ void fft_passes(Lds s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_passes(Lds s, TwPtr __restrict__ tw, int tid) {
   if constexpr (P < num_passes(L)) {
     fft_pass<L, T, P, INV>(s, tw, tid);
     fft_passes<L, T, INV, P + 1>(s, tw, tid);
@@ -248,7 +265,7 @@ __device__ __forceinline__ void fft_passes(Lds s, const float2* __restrict__ tw,
 // The caller must have synchronised after filling s; on return s holds the
 // result and the workgroup has synchronised.
 template <int L, int T, bool INV>
-__device__ __forceinline__ void fft_lds(Lds s, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_lds(Lds s, TwPtr __restrict__ tw, int tid) {
   static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
   fft_passes<L, T, INV>(s, tw, tid);
 }

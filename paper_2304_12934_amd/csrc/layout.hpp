@@ -13,10 +13,16 @@ struct SpreadItem {
 };
 enum { kItemAtomic = 1, kItemDC = 2 };
 
+// Interpolation tiles: a point belongs to the tile holding its first tap; the
+// kernel stages the tile plus W + 1 cells (the footprint and a one-cell
+// margin on each side) of the grid in LDS.  Interpolation items reuse
+// SpreadItem with flags = bound = 0.
+constexpr int kInterpTileW = 64, kInterpTileH = 32;
+
 // One slice as the kernels see it (device resident, filled at bind time).
 // Complex buffers are float pairs.
 struct SliceDesc {
-  int32_t N, Nt, na, G, H, rows, cols, tiles_x, n_items, n_zero, slot, pad;
+  int32_t N, Nt, na, G, H, rows, cols, tiles_x, n_items, n_zero, slot, itiles_x;
   int64_t vol_off, sino_off;      // element offsets into the caller's buffers
   const float* deapod;            // [N] 1/phihat((i - N/2)/G)
   const float* tw_G;              // [G] exp(-2 pi i m/G)
@@ -29,6 +35,8 @@ struct SliceDesc {
   const int32_t* pts;             // spreading point lists (tile-major)
   const SpreadItem* items;        // spreading work items of this slice's geometry
   const int32_t* zero_tiles;      // tiles written by several items
+  const int32_t* ipts;            // interpolation point lists (tile-major, every point once)
+  const SpreadItem* iitems;       // interpolation work items (tile, point range)
 };
 
 // One unit of work of a stage launch: (slice index in the plan, unit index

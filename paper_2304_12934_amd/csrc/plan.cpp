@@ -226,6 +226,48 @@ void build_spread_bins(const Plan& plan, Geom& g) {
   });
 }
 
+void build_interp_bins(const Plan& plan, Geom& g) {
+  const int W = plan.kb.W;
+  const int na = g.key.n_angles;
+  const int TW = kInterpTileW, TH = kInterpTileH;
+  g.itiles_x = (g.cols + TW - 1) / TW;
+  g.itiles_y = (g.rows + TH - 1) / TH;
+  const int ntiles = g.itiles_x * g.itiles_y;
+  const double halfW = 0.5 * W;
+  // the tile of the first tap (g0x, g0y) in grid row/column coordinates; the
+  // same double arithmetic as the kernels, which stage a one-cell margin anyway
+  auto tile_of = [&](int a, int j) {
+    const int g0x = int(std::ceil(double(j) * g.gxy[2 * a] - halfW));
+    const int g0y = int(std::ceil(double(j) * g.gxy[2 * a + 1] - halfW));
+    const int r = g0x + plan.halo, c = g0y + g.G / 2 + plan.colpad;
+    return (r / TH) * g.itiles_x + c / TW;
+  };
+  std::vector<int32_t> start(size_t(ntiles) + 1, 0);
+  for (int a = 0; a < na; ++a)
+    for (int j = 0; j < g.H; ++j) start[size_t(tile_of(a, j)) + 1]++;
+  for (int t = 0; t < ntiles; ++t) start[size_t(t) + 1] += start[size_t(t)];
+  g.ipts.assign(size_t(start[size_t(ntiles)]), 0);
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  // angle-major within a tile: neighbouring threads take neighbouring points of one line
+  for (int a = 0; a < na; ++a)
+    for (int j = 0; j < g.H; ++j) g.ipts[size_t(fill[size_t(tile_of(a, j))]++)] = a * g.H + j;
+  const int chunk = plan.tune.chunk;
+  g.iitems.clear();
+  for (int t = 0; t < ntiles; ++t) {
+    const int b = start[size_t(t)], e = start[size_t(t) + 1];
+    if (e == b) continue;
+    const int n_items = (e - b + chunk - 1) / chunk;
+    for (int k = 0; k < n_items; ++k) {
+      const int ib = b + int((int64_t(e - b) * k) / n_items);
+      const int ie = b + int((int64_t(e - b) * (k + 1)) / n_items);
+      g.iitems.push_back({t, ib, ie, 0, 0});
+    }
+  }
+  std::stable_sort(g.iitems.begin(), g.iitems.end(), [](const SpreadItem& x, const SpreadItem& y) {
+    return (x.end - x.begin) > (y.end - y.begin);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
@@ -389,7 +431,15 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     err = "chunk must be in [64, 65536]";
     return NR_INVALID_ARG;
   }
-  for (Geom& g : plan.geoms) build_spread_bins(plan, g);
+  for (Geom& g : plan.geoms) {
+    build_spread_bins(plan, g);
+    if (tu.interp_mode == 0) build_interp_bins(plan, g);
+    else {
+      g.itiles_x = g.itiles_y = 0;
+      g.ipts.clear();
+      g.iitems.clear();
+    }
+  }
 
   const int ns = int(plan.slices.size());
   // per-slice scratch: T, ext and yh, each 256-byte aligned
@@ -458,33 +508,47 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     };
     for (int G : Gs) add(bt.fwd, Stage::FwdRows, G, true, true, row_pairs);
     for (int G : Gs) add(bt.fwd, Stage::FwdCols, G, true, false, columns);
-    for (int L : Nts) add(bt.fwd, Stage::FwdInterp, L, false, true, angle_pairs);
-    for (int L : Nts) add(bt.adj, Stage::AdjRadial, L, false, false, angle_pairs);
-    add(bt.adj, Stage::SpreadZero, 0, true, false, [](int s, const Geom& g, std::vector<WorkItem>& v) {
-      for (int u = 0; u < int(g.zero_tiles.size()); ++u) v.push_back({s, u});
-    });
-    {
-      // spreading items of the whole batch, heaviest first
+    // items of heavy tiles (near the origin) first, over every slice of the batch
+    auto heaviest_first = [&](Stage st, auto&& items_of) {
       std::vector<WorkItem> logical;
       std::vector<int> weight;
       for (int s : bt.slices) {
         const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(s)])];
-        for (int u = 0; u < int(g.items.size()); ++u) logical.push_back({s, u});
+        const std::vector<SpreadItem>& its = items_of(g);
+        for (int u = 0; u < int(its.size()); ++u) {
+          logical.push_back({s, u});
+          weight.push_back(its[size_t(u)].end - its[size_t(u)].begin);
+        }
       }
+      if (logical.empty()) return std::vector<StageLaunch>{};
       std::vector<size_t> order(logical.size());
       for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-      auto w = [&](size_t i) {
-        const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(logical[i].slice)])];
-        const SpreadItem& it = g.items[size_t(logical[i].unit)];
-        return it.end - it.begin;
-      };
-      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return w(a) > w(b); });
+      std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return weight[a] > weight[b]; });
       std::vector<WorkItem> sorted;
       for (size_t i : order) sorted.push_back(logical[i]);
-      StageLaunch sl{Stage::Spread, 0, plan.work.size() * sizeof(WorkItem), int(sorted.size())};
+      StageLaunch sl{st, 0, plan.work.size() * sizeof(WorkItem), int(sorted.size())};
       append_units(plan.work, sorted, false);
-      bt.adj.push_back(sl);
+      return std::vector<StageLaunch>{sl};
+    };
+    if (tu.interp_mode == 0) {
+      for (const StageLaunch& sl : heaviest_first(Stage::FwdInterp, [](const Geom& g) -> const std::vector<SpreadItem>& {
+             return g.iitems;
+           }))
+        bt.fwd.push_back(sl);
+      for (int L : Nts) add(bt.fwd, Stage::FwdRadial, L, false, true, angle_pairs);
+    } else {
+      for (int L : Nts) add(bt.fwd, Stage::FwdInterp, L, false, true, angle_pairs);
     }
+    for (int L : Nts) add(bt.adj, Stage::AdjRadial, L, false, false, angle_pairs);
+    add(bt.adj, Stage::SpreadZero, 0, true, false, [](int s, const Geom& g, std::vector<WorkItem>& v) {
+      for (int u = 0; u < int(g.zero_tiles.size()); ++u) v.push_back({s, u});
+    });
+    // spreading items of the whole batch, heaviest first (every tile has at
+    // least one item, so the launch always exists)
+    for (const StageLaunch& sl : heaviest_first(Stage::Spread, [](const Geom& g) -> const std::vector<SpreadItem>& {
+           return g.items;
+         }))
+      bt.adj.push_back(sl);
     for (int G : Gs) add(bt.adj, Stage::AdjCols, G, true, false, columns);
     for (int G : Gs) add(bt.adj, Stage::AdjRows, G, true, true, row_pairs);
     plan.batches.push_back(std::move(bt));
@@ -511,6 +575,10 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     off = align_up(off + g.items.size() * sizeof(SpreadItem), 256);
     g.off_zero = off;
     off = align_up(off + std::max<size_t>(1, g.zero_tiles.size()) * sizeof(int32_t), 256);
+    g.off_ipts = off;
+    off = align_up(off + std::max<size_t>(1, g.ipts.size()) * sizeof(int32_t), 256);
+    g.off_iitems = off;
+    off = align_up(off + std::max<size_t>(1, g.iitems.size()) * sizeof(SpreadItem), 256);
   }
   plan.off_desc = off;
   off = align_up(off + size_t(ns) * sizeof(SliceDesc), 256);
@@ -557,6 +625,9 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.pts = reinterpret_cast<const int32_t*>(d_ws + g.off_pts);
       d.items = reinterpret_cast<const SpreadItem*>(d_ws + g.off_items);
       d.zero_tiles = reinterpret_cast<const int32_t*>(d_ws + g.off_zero);
+      d.itiles_x = g.itiles_x;
+      d.ipts = reinterpret_cast<const int32_t*>(d_ws + g.off_ipts);
+      d.iitems = reinterpret_cast<const SpreadItem*>(d_ws + g.off_iitems);
       out[size_t(s)] = d;
     }
   }

@@ -71,8 +71,12 @@ struct Geom {
   std::vector<int32_t> tile_start;  // tiles_x*tiles_y + 1 offsets into pts
   std::vector<SpreadItem> items;
   std::vector<int32_t> zero_tiles;  // tiles written by atomic items: cleared first
+  // interpolation bins (every point j >= 0 once, by the tile of its first tap)
+  int itiles_x = 0, itiles_y = 0;
+  std::vector<int32_t> ipts;
+  std::vector<SpreadItem> iitems;
   // workspace offsets (bytes)
-  size_t off_gxy = 0, off_flip = 0, off_pts = 0, off_items = 0, off_zero = 0;
+  size_t off_gxy = 0, off_flip = 0, off_pts = 0, off_items = 0, off_zero = 0, off_ipts = 0, off_iitems = 0;
 };
 
 // Tunable execution parameters: none changes results beyond float32 rounding
@@ -83,11 +87,14 @@ struct Tuning {
   int batch = 0;                  // most slices per batched launch (0: no limit)
   int batch_mb = 160;             // scratch budget of one batch in MiB (a lone slice may exceed it)
   int spread_mode = 0;            // 0: LDS tiles, 1: global atomics (reference)
+  int interp_mode = 0;            // 0: LDS tiles + radial pass, 1: direct gathers per angle pair
 };
 
-// Stages of the forward chain (FwdRows, FwdCols, FwdInterp) and of the
+// Stages of the forward chain (FwdRows, FwdCols, FwdInterp, FwdRadial) and of the
 // adjoint chain (AdjRadial, SpreadZero, Spread, AdjCols, AdjRows).
-enum class Stage : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero, Count };
+enum class Stage : int {
+  FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero, FwdRadial, Count
+};
 
 // One kernel launch of a batch: every unit of `stage` over the batch's
 // slices whose FFT length is L, listed at work_off in the workspace.
@@ -145,5 +152,8 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws);
 
 // Fills the spreading bins of one geometry (called by layout_plan).
 void build_spread_bins(const Plan& plan, Geom& g);
+
+// Fills the interpolation bins of one geometry (called by layout_plan).
+void build_interp_bins(const Plan& plan, Geom& g);
 
 }  // namespace nr

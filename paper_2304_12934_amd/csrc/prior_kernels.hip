@@ -20,127 +20,176 @@ namespace nrk {
 namespace {
 
 // Block of 64 x 8 x 8 voxels (x, y, z), 512 threads: thread (lx, ly) owns the
-// z-column of 8 voxels.  The block stages its voxels with a one-voxel halo.
+// z-column of 8 voxels (one wavefront per x-row).  The block stages its voxels
+// with a one-voxel halo in F; staged index of block-local (x, y, z), each in
+// [-1, T], is (z+1)*FP + (y+1)*FX + (x+1).  The pair terms of one direction go
+// to R (same indexing, z in [-1, TZ)), double-buffered across directions.
 constexpr int TX = 64, TY = 8, TZ = 8;
 constexpr int NT = TX * TY;
-constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2;   // staged block (halo on every side)
-constexpr int RX = TX + 2, RY = TY + 2, RZ = TZ + 1;   // pair terms: x, y in [-1, T], z in [-1, T)
+constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2;
+constexpr int FP = FX * FY;
+constexpr int RSZ = (TZ + 1) * FP;
 
 __device__ __forceinline__ float pow_2mp(float a, float e) {   // a^e for a > 0
   return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(a));   // v_exp_f32, v_log_f32 (base 2)
 }
 
-// rho'(u) and, with VALUE, rho(u)
+// w rho'(u) and, with VALUE, w rho(u).  s = |u|^(2-p) is taken as 0 at u = 0
+// (a select, no branch); both results are 0 there whatever s is.
 template <bool VALUE>
-__device__ __forceinline__ float rho_prime(float u, const PriorArgs& pr, float& rho) {
+__device__ __forceinline__ float rho_prime(float u, const PriorArgs& pr, float w, float& rho) {
   const float a = fabsf(u);
-  if (a == 0.f) {
+  const float s = a > 0.f ? pow_2mp(a, 2.f - pr.p) : 0.f;
+  const float inv = __builtin_amdgcn_rcpf(pr.c + s);
+  if (VALUE) rho = w * a * a * inv;
+  return w * u * fmaf(pr.p, s, 2.f * pr.c) * inv * inv;
+}
+
+struct BlockCtx {
+  int x0, y0, z0, n, nz, lx, ly, tid;
+  float inv_sigma;
+  __device__ __forceinline__ bool inside(int bx, int by, int bz) const {   // block-local coordinates
+    const int x = x0 + bx, y = y0 + by, z = z0 + bz;
+    return x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < nz;
+  }
+};
+
+__device__ __forceinline__ constexpr int fidx(int bx, int by, int bz) { return (bz + 1) * FP + (by + 1) * FX + (bx + 1); }
+
+// r_d at block-local m = (bx, by, bz): w rho'((f_m - f_{m+d})/sigma), 0 when m
+// or m + d lies outside the volume.
+template <bool VALUE, bool INTERIOR, int DZ, int DY, int DX>
+__device__ __forceinline__ float pair_term(const BlockCtx& b, const float* F, float fm, float fn, int bx, int by,
+                                           int bz, const PriorArgs& pr, float w, float& rho) {
+  if (!INTERIOR && !(b.inside(bx, by, bz) && b.inside(bx + DX, by + DY, bz + DZ))) {
     rho = 0.f;
     return 0.f;
   }
-  const float s = pow_2mp(a, 2.f - pr.p);
-  const float inv = 1.f / (pr.c + s);
-  if (VALUE) rho = a * a * inv;
-  return u * (2.f * pr.c + pr.p * s) * inv * inv;
+  return rho_prime<VALUE>((fm - fn) * b.inv_sigma, pr, w, rho);
 }
 
-// The 13 neighbour offsets (dz, dy, dx) that are lexicographically positive;
-// the other 13 are their negations.
-__constant__ int8_t kDirs[13][3] = {{0, 0, 1},  {0, 1, -1},  {0, 1, 0},  {0, 1, 1},  {1, -1, -1},
-                                    {1, -1, 0}, {1, -1, 1}, {1, 0, -1}, {1, 0, 0},  {1, 0, 1},
-                                    {1, 1, -1}, {1, 1, 0},  {1, 1, 1}};
+// One of the 13 lexicographically positive offsets d = (DZ, DY, DX).  Each
+// unordered pair (m, m + d) is evaluated once: r_d(m) enters voxel m with +
+// and voxel m + d with - (rho' is odd), so voxel m gathers r_d(m) - r_d(m - d).
+// The terms r_d(m - d) of the block's own voxels come from the thread that owns
+// column m - d or, off the block, from the halo rows evaluated here.
+template <bool VALUE, bool INTERIOR, int DZ, int DY, int DX>
+__device__ __forceinline__ void direction(const BlockCtx& b, const float* F, float* R, const float (&fc)[FZ],
+                                          float (&acc)[TZ], float& hsum, const PriorArgs& pr) {
+  constexpr int d2 = DZ * DZ + DY * DY + DX * DX;
+  const float w = d2 == 1 ? pr.w_face : (d2 == 2 ? pr.w_edge : pr.w_corner);
+  constexpr int ZLO = -DZ;
+  float r[TZ + 1];   // r[z + 1] for z in [ZLO, TZ)
+#pragma unroll
+  for (int z = ZLO; z < TZ; ++z) {
+    const float fn = (DX == 0 && DY == 0) ? fc[z + 1 + DZ] : F[fidx(b.lx + DX, b.ly + DY, z + DZ)];
+    float rho;
+    r[z + 1] = pair_term<VALUE, INTERIOR, DZ, DY, DX>(b, F, fc[z + 1], fn, b.lx, b.ly, z, pr, w, rho);
+    if (VALUE && z >= 0) hsum += 2.f * rho;
+  }
+  if constexpr (DX == 0 && DY == 0) {   // d = (1, 0, 0): the partner term is in this thread
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) acc[z] += r[z + 1] - r[z];
+    return;
+  } else {
+#pragma unroll
+    for (int z = ZLO; z < TZ; ++z) R[fidx(b.lx, b.ly, z)] = r[z + 1];
+    float rho;
+    if constexpr (DY != 0) {   // the row y = -1 (DY > 0) or y = TY (DY < 0) of m - d: one term per thread
+      constexpr int yh = DY > 0 ? -1 : TY;
+      const int xh = (b.tid & (TX - 1)) - DX, zh = (b.tid / TX) - DZ;
+      R[fidx(xh, yh, zh)] = pair_term<false, INTERIOR, DZ, DY, DX>(
+          b, F, F[fidx(xh, yh, zh)], F[fidx(xh + DX, yh + DY, zh + DZ)], xh, yh, zh, pr, w, rho);
+    }
+    if constexpr (DX != 0) {   // the column x = -1 (DX > 0) or x = TX (DX < 0): 64 terms, first wavefront
+      constexpr int xh = DX > 0 ? -1 : TX;
+      if (b.tid < TY * TZ) {
+        const int yh = (b.tid % TY) - DY, zh = (b.tid / TY) - DZ;
+        R[fidx(xh, yh, zh)] = pair_term<false, INTERIOR, DZ, DY, DX>(
+            b, F, F[fidx(xh, yh, zh)], F[fidx(xh + DX, yh + DY, zh + DZ)], xh, yh, zh, pr, w, rho);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) acc[z] += R[fidx(b.lx, b.ly, z)] - R[fidx(b.lx - DX, b.ly - DY, z - DZ)];
+  }
+  // Materialise the sums here: otherwise the compiler sinks every direction's
+  // adds into the guarded store at the end and keeps all loaded terms live.
+#pragma unroll
+  for (int z = 0; z < TZ; ++z) asm volatile("" : "+v"(acc[z]));
+  if (VALUE) asm volatile("" : "+v"(hsum));
+}
 
 }  // namespace
 
-// Each unordered neighbour pair (m, m + d) is evaluated once: r_d(m) =
-// w_d rho'((f_m - f_{m+d})/sigma) enters voxel m with + and voxel m + d with -
-// (rho' is odd).  Per direction the block evaluates r_d on its voxels and on
-// their one-voxel shift by -d, in LDS, then every voxel adds r_d(m) - r_d(m-d).
 template <bool VALUE, bool INTERIOR>
 __device__ __forceinline__ void qggmrf_block(const float* __restrict__ f, float* __restrict__ grad,
-                                             double* __restrict__ value, int nz, int n, const PriorArgs& pr,
-                                             float scale, float* F, float* R, double* red) {
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
-  const size_t plane = size_t(n) * n;
-  for (int i = tid; i < FX * FY * FZ; i += NT) {
-    const int bx = i % FX, by = (i / FX) % FY, bz = i / (FX * FY);
-    const int x = x0 + bx - 1, y = y0 + by - 1, z = z0 + bz - 1;
+                                             double* __restrict__ value, const BlockCtx& b, const PriorArgs& pr,
+                                             float scale, float* F, float* R0, float* R1, double* red) {
+  const size_t plane = size_t(b.n) * b.n;
+  for (int i = b.tid; i < FZ * FP; i += NT) {
+    const int bx = i % FX - 1, by = (i / FX) % FY - 1, bz = i / FP - 1;
     float v = 0.f;
-    if (INTERIOR || (x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < nz))
-      v = f[size_t(z) * plane + size_t(y) * n + x];
+    if (INTERIOR || b.inside(bx, by, bz)) v = f[size_t(b.z0 + bz) * plane + size_t(b.y0 + by) * b.n + (b.x0 + bx)];
     F[i] = v;
   }
   __syncthreads();
-  const float inv_sigma = 1.f / pr.sigma;
-  const int lx = tid % TX, ly = tid / TX;
+  float fc[FZ];
+#pragma unroll
+  for (int k = 0; k < FZ; ++k) fc[k] = F[fidx(b.lx, b.ly, k - 1)];
   float acc[TZ];
 #pragma unroll
   for (int z = 0; z < TZ; ++z) acc[z] = 0.f;
   float hsum = 0.f;
-  auto inside = [&](int bz, int by, int bx) {   // block-local coordinates, -1..T
-    const int x = x0 + bx, y = y0 + by, z = z0 + bz;
-    return x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < nz;
-  };
-#pragma unroll 1
-  for (int k = 0; k < 13; ++k) {
-    const int dz = kDirs[k][0], dy = kDirs[k][1], dx = kDirs[k][2];
-    const int d2 = dz * dz + dy * dy + dx * dx;
-    const float w = d2 == 1 ? pr.w_face : (d2 == 2 ? pr.w_edge : pr.w_corner);
-    // region: the block and its shift by -d
-    const int xa = dx > 0 ? -1 : 0, xb = dx < 0 ? TX + 1 : TX;
-    const int ya = dy > 0 ? -1 : 0, yb = dy < 0 ? TY + 1 : TY;
-    const int za = dz > 0 ? -1 : 0;
-    const int ex = xb - xa, ey = yb - ya, ez = TZ - za;
-    for (int i = tid; i < ex * ey * ez; i += NT) {
-      const int bx = xa + i % ex, by = ya + (i / ex) % ey, bz = za + i / (ex * ey);
-      float r = 0.f, rh = 0.f;
-      if (INTERIOR || (inside(bz, by, bx) && inside(bz + dz, by + dy, bx + dx))) {
-        const float fm = F[(bz + 1) * FY * FX + (by + 1) * FX + (bx + 1)];
-        const float fn = F[(bz + 1 + dz) * FY * FX + (by + 1 + dy) * FX + (bx + 1 + dx)];
-        r = w * rho_prime<VALUE>((fm - fn) * inv_sigma, pr, rh);
-        // the value counts each ordered pair: 2 w rho per unordered pair, once (at its owned m)
-        if (VALUE && bx >= 0 && bx < TX && by >= 0 && by < TY && bz >= 0) hsum += 2.f * w * rh;
-      }
-      R[(bz + 1) * RY * RX + (by + 1) * RX + (bx + 1)] = r;
-    }
-    __syncthreads();
+  // R buffers alternate between the directions that exchange terms through LDS,
+  // so one barrier per direction suffices.
+  direction<VALUE, INTERIOR, 1, 0, 0>(b, F, nullptr, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 0, 0, 1>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 0, 1, -1>(b, F, R1, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 0, 1, 0>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 0, 1, 1>(b, F, R1, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, -1, -1>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, -1, 0>(b, F, R1, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, -1, 1>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, 0, -1>(b, F, R1, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, 0, 1>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, 1, -1>(b, F, R1, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, 1, 0>(b, F, R0, fc, acc, hsum, pr);
+  direction<VALUE, INTERIOR, 1, 1, 1>(b, F, R1, fc, acc, hsum, pr);
+  const float gscale = scale * 2.f * pr.lambda * b.inv_sigma;
+  const int x = b.x0 + b.lx, y = b.y0 + b.ly;
+  if (x < b.n && y < b.n) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
-      acc[z] += R[(z + 1) * RY * RX + (ly + 1) * RX + (lx + 1)] -
-                R[(z + 1 - dz) * RY * RX + (ly + 1 - dy) * RX + (lx + 1 - dx)];
-    __syncthreads();
-  }
-  const float gscale = scale * 2.f * pr.lambda * inv_sigma;
-  const int x = x0 + lx, y = y0 + ly;
-  if (x < n && y < n) {
-#pragma unroll
-    for (int z = 0; z < TZ; ++z)
-      if (z0 + z < nz) grad[size_t(z0 + z) * plane + size_t(y) * n + x] += gscale * acc[z];
+      if (b.z0 + z < b.nz) grad[size_t(b.z0 + z) * plane + size_t(y) * b.n + x] += gscale * acc[z];
   }
   if (VALUE) {
-    red[tid] = double(hsum);
+    red[b.tid] = double(hsum);
     __syncthreads();
     for (int w = NT / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
+      if (b.tid < w) red[b.tid] += red[b.tid + w];
       __syncthreads();
     }
-    if (tid == 0) atomicAdd(value, double(pr.lambda) * red[0]);
+    if (b.tid == 0) atomicAdd(value, double(pr.lambda) * red[0]);
   }
 }
 
 template <bool VALUE>
-__global__ __launch_bounds__(NT) void k_qggmrf(const float* __restrict__ f, float* __restrict__ grad,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_qggmrf(const float* __restrict__ f, float* __restrict__ grad,
                                                double* __restrict__ value, int nz, int n, PriorArgs pr,
                                                float scale) {
-  __shared__ float F[FZ * FY * FX];
-  __shared__ float R[RZ * RY * RX];
-  __shared__ double red[NT];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  __shared__ float F[FZ * FP];
+  __shared__ float R0[RSZ], R1[RSZ];
+  __shared__ double red[VALUE ? NT : 1];
+  BlockCtx b;
+  b.x0 = blockIdx.x * TX, b.y0 = blockIdx.y * TY, b.z0 = blockIdx.z * TZ;
+  b.n = n, b.nz = nz, b.tid = threadIdx.x, b.lx = threadIdx.x % TX, b.ly = threadIdx.x / TX;
+  b.inv_sigma = 1.f / pr.sigma;
   // interior block: the block and its halo lie inside the volume
-  const bool interior = x0 >= 1 && x0 + TX + 1 <= n && y0 >= 1 && y0 + TY + 1 <= n && z0 >= 1 && z0 + TZ + 1 <= nz;
-  if (interior) qggmrf_block<VALUE, true>(f, grad, value, nz, n, pr, scale, F, R, red);
-  else qggmrf_block<VALUE, false>(f, grad, value, nz, n, pr, scale, F, R, red);
+  const bool interior =
+      b.x0 >= 1 && b.x0 + TX + 1 <= n && b.y0 >= 1 && b.y0 + TY + 1 <= n && b.z0 >= 1 && b.z0 + TZ + 1 <= nz;
+  if (interior) qggmrf_block<VALUE, true>(f, grad, value, b, pr, scale, F, R0, R1, red);
+  else qggmrf_block<VALUE, false>(f, grad, value, b, pr, scale, F, R0, R1, red);
 }
 
 __global__ void k_set_double(double* p, double v) { *p = v; }

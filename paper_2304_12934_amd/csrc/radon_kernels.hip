@@ -13,16 +13,18 @@
 //                              Halo cells hold copies (periodic qy) and
 //                              conjugate mirrors (qx < 0 and qx > G/2, by
 //                              Hermitian symmetry of a real slice).
-//   yh   [n_angles][N_t/2+1]   half-line spectra of the adjoint input
+//   yh   [n_angles][N_t/2+1]   half-line spectra (interpolated values in the
+//                              forward chain, the adjoint input's in the adjoint)
 //
 // Forward (Sec. 2.2, eqs. "nufft"-"nufft3" in reverse order):
 //   F1 k_fwd_rows   divide by phihat(x/G) phihat(y/G), zero-pad to G,
 //                   R2C along x for two rows at once, write T transposed
 //   F2 k_fwd_cols   C2C along y per kept qx, write ext (with halo cells)
-//   F3+F4 k_fwd_interp  per pair of angles: WxW Kaiser-Bessel interpolation
-//                   onto the half-line k_j = j/N_t, then the 1D inverse DFT
-//                   along the line (Hermitian, two angles packed in one
-//                   complex transform), 1/N_t, real sinogram rows
+//   F3 k_interp_tiles  WxW Kaiser-Bessel interpolation onto the half-lines
+//                   k_j = j/N_t from LDS-staged grid tiles, into yh
+//   F4 k_fwd_radial  the 1D inverse DFT along each line (Hermitian, two
+//                   angles packed in one complex transform), real sinogram rows
+//   (F3+F4 k_fwd_interp does both per angle pair, gathering from the grid)
 // Adjoint (Sec. 3, eq. "transpose"): the transpose of every step in reverse:
 //   A1 k_adj_radial  R2C of two sinogram rows, weights c_j/N_t
 //   A2 k_spread_*    WxW spreading onto ext (LDS tiles, or plain atomics)
@@ -80,10 +82,63 @@ __device__ __forceinline__ void point_taps(double gx, double gy, int j, const KB
   }
 }
 
+// Pointers read from device memory are generic to the compiler, which then
+// emits flat loads (slower to issue, and counted against the LDS wait counter
+// too). Every buffer a slice descriptor points to is global memory, so the
+// kernels see the descriptor with global-typed pointers.
+struct DSlice {
+  int N, Nt, na, G, H, rows, cols, tiles_x;
+  int64_t vol_off, sino_off;
+  const NR_G float* deapod;
+  const NR_G float2* tw_G;
+  const NR_G float2* tw_Nt;
+  const NR_G double* gxy;
+  const NR_G int32_t* flip;
+  NR_G float2* T;
+  NR_G float2* ext;
+  NR_G float2* yh;
+  const NR_G int32_t* pts;
+  const NR_G SpreadItem* items;
+  const NR_G int32_t* zero_tiles;
+  const NR_G int32_t* ipts;
+  const NR_G SpreadItem* iitems;
+  int itiles_x;
+};
+
+// The slice descriptor by value (uniform: scalar loads).
+__device__ __forceinline__ DSlice load_desc(const SliceDesc* p) {
+  const SliceDesc s = *p;
+  DSlice d;
+  d.N = s.N, d.Nt = s.Nt, d.na = s.na, d.G = s.G, d.H = s.H, d.rows = s.rows, d.cols = s.cols;
+  d.tiles_x = s.tiles_x;
+  d.vol_off = s.vol_off, d.sino_off = s.sino_off;
+  d.deapod = (const NR_G float*)s.deapod;
+  d.tw_G = (const NR_G float2*)s.tw_G;
+  d.tw_Nt = (const NR_G float2*)s.tw_Nt;
+  d.gxy = (const NR_G double*)s.gxy;
+  d.flip = (const NR_G int32_t*)s.flip;
+  d.T = (NR_G float2*)s.T;
+  d.ext = (NR_G float2*)s.ext;
+  d.yh = (NR_G float2*)s.yh;
+  d.pts = (const NR_G int32_t*)s.pts;
+  d.items = (const NR_G SpreadItem*)s.items;
+  d.zero_tiles = (const NR_G int32_t*)s.zero_tiles;
+  d.ipts = (const NR_G int32_t*)s.ipts;
+  d.iitems = (const NR_G SpreadItem*)s.iitems;
+  d.itiles_x = s.itiles_x;
+  return d;
+}
+
 template <int L>
 __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
   return x < 0 ? x + L : (x >= L ? x - L : x);
 }
+
+// for (int n = tid; n < COUNT; n += T) with a compile-time trip count, so
+// that the compiler unrolls it and issues all of its loads before waiting
+#define NR_STRIDED(n, COUNT, T)                                                                       \
+  _Pragma("unroll") for (int n##_it = 0, n = tid; n##_it < ((COUNT) + (T)-1) / (T); ++n##_it, n += (T)) \
+    if ((COUNT) % (T) == 0 || n < (COUNT))
 
 // Every kernel runs one unit of its work list per workgroup (block b takes
 // entry b); padding entries (slice < 0) and blocks past the list do nothing.
@@ -102,27 +157,22 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(LaunchArgs a) {
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
-    const int N = d.N;
+    const DSlice d = load_desc(a.descs + wi.slice);
+    constexpr int N = L / 2;   // G = 2N
     const int iy0 = 2 * wi.unit;
     const float* __restrict__ f0 = a.vol_in + d.vol_off + size_t(iy0) * N;
     const float d0 = d.deapod[iy0], d1 = d.deapod[iy0 + 1];
-    // x = ix - N/2 sits at index x mod L
-    for (int n = tid; n < L; n += T) {
-      const int ix = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
-      float2 v = make_float2(0.f, 0.f);
-      if (ix >= 0) {
-        const float dx = d.deapod[ix];
-        v.x = dx * d0 * f0[ix];
-        v.y = dx * d1 * f0[N + ix];
-      }
-      s[n] = v;
+    // x = ix - N/2 sits at index x mod L; indices N/2 .. L - N/2 - 1 are the zero padding
+    NR_STRIDED(ix, N, T) {
+      const float dx = d.deapod[ix];
+      s[ix < N / 2 ? ix + L - N / 2 : ix - N / 2] = make_float2(dx * d0 * f0[ix], dx * d1 * f0[N + ix]);
     }
+    NR_STRIDED(k, N, T) s[N / 2 + k] = make_float2(0.f, 0.f);
     __syncthreads();
-    fft_lds<L, T, false>(s, c2(d.tw_G), tid);
+    fft_lds<L, T, false>(s, d.tw_G, tid);
     // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
-    float4* __restrict__ out = reinterpret_cast<float4*>(d.T);
-    for (int q = tid; q <= L / 2; q += T) {
+    NR_G float4* __restrict__ out = (NR_G float4*)d.T;
+    NR_STRIDED(q, L / 2 + 1, T) {
       const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
       float4 o;
       o.x = 0.5f * (z1.x + z2.x);
@@ -141,7 +191,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(LaunchArgs a) {
 
 // store v at natural frequency index n of a grid row (and its periodic copies)
 template <int L>
-__device__ __forceinline__ void store_row(float2* row, int colpad, int n, float2 v) {
+__device__ __forceinline__ void store_row(NR_G float2* row, int colpad, int n, float2 v) {
   const int p = wrap_index<L>(n + L / 2) + colpad;
   row[p] = v;
   if (p >= L) row[p - L] = v;                            // left pad: qy < -L/2
@@ -156,22 +206,21 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
   const int tid = threadIdx.x;
   const int halo = a.halo, colpad = a.colpad;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
-    const int N = d.N, cols = d.cols;
+    const DSlice d = load_desc(a.descs + wi.slice);
+    constexpr int N = L / 2;   // G = 2N
+    const int cols = d.cols;
     const int qx = wi.unit;
-    const float2* __restrict__ col = c2(d.T) + size_t(qx) * N;
-    for (int n = tid; n < L; n += T) {
-      const int iy = n < N / 2 ? n + N / 2 : (n >= L - N / 2 ? n - L + N / 2 : -1);
-      s[n] = iy >= 0 ? col[iy] : make_float2(0.f, 0.f);
-    }
+    const NR_G float2* __restrict__ col = d.T + size_t(qx) * N;
+    NR_STRIDED(iy, N, T) s[iy < N / 2 ? iy + L - N / 2 : iy - N / 2] = col[iy];
+    NR_STRIDED(k, N, T) s[N / 2 + k] = make_float2(0.f, 0.f);
     __syncthreads();
-    fft_lds<L, T, false>(s, c2(d.tw_G), tid);
-    float2* ext = c2(d.ext);
-    float2* row = ext + size_t(qx + halo) * cols;
+    fft_lds<L, T, false>(s, d.tw_G, tid);
+    NR_G float2* ext = d.ext;
+    NR_G float2* row = ext + size_t(qx + halo) * cols;
     // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
-    float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
-    float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    for (int n = tid; n < L; n += T) {
+    NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+    NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+    NR_STRIDED(n, L, T) {
       const float2 v = s[n];
       store_row<L>(row, colpad, n, v);
       const int nm = n == 0 ? 0 : L - n;
@@ -187,12 +236,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 
 template <int W>
-__device__ __forceinline__ float2 interp_point(const SliceDesc& d, int halo, int colpad, const KBArgs& kb,
+__device__ __forceinline__ float2 interp_point(const DSlice& d, int halo, int colpad, const KBArgs& kb,
                                                int ang, int j) {
   int g0x, g0y;
   float wx[W], wy[W];
   point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
-  const float2* __restrict__ p = c2(d.ext) + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
+  const NR_G float2* __restrict__ p = d.ext + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
   float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
   for (int i = 0; i < W; ++i) {
@@ -219,7 +268,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
   const int tid = threadIdx.x;
   const float inv = 1.0f / float(L);
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
+    const DSlice d = load_desc(a.descs + wi.slice);
     const int a0 = 2 * wi.unit, a1 = a0 + 1;
     const bool has1 = a1 < d.na;
     // both half-lines per iteration (two independent gathers in flight), packed
@@ -235,10 +284,100 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
       if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
     }
     __syncthreads();
-    fft_lds<L, T, true>(s, c2(d.tw_Nt), tid);
+    fft_lds<L, T, true>(s, d.tw_Nt, tid);
     // bin m (t = m - N_t/2) is output index t mod N_t
     float* __restrict__ o0 = a.sino_out + d.sino_off + size_t(a0) * L;
-    for (int m = tid; m < L; m += T) {
+    NR_STRIDED(m, L, T) {
+      const float2 z = s[wrap_index<L>(m + L / 2)];
+      o0[m] = z.x;
+      if (has1) o0[L + m] = z.y;
+    }
+    __syncthreads();
+  }
+}
+
+// F3 from LDS tiles: one work item = one interpolation tile and a range of the
+// points whose first tap lies in it.  The workgroup stages the tile with the
+// W-1 cells the footprints reach past it and a one-cell margin on each side,
+// then every thread interpolates its points from LDS (the same sums, in the
+// same order, as interp_point) into the half-line buffer yh, scaled by 1/N_t.
+template <int W>
+__global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
+  constexpr int TW = kInterpTileW, TH = kInterpTileH;
+  constexpr int RW = TW + W + 1, RH = TH + W + 1;
+  __shared__ float2 reg[RH * RW];
+  const int tid = threadIdx.x;
+  constexpr int T = 256;
+  NR_FOR_EACH_UNIT(a, wi) {
+    const DSlice d = load_desc(a.descs + wi.slice);
+    const SpreadItem it = d.iitems[wi.unit];
+    const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 1;
+    const NR_G float2* __restrict__ ext = d.ext;
+    // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
+    NR_STRIDED(c, RH * RW, T) {
+      const int r = min(max(r0 + c / RW, 0), d.rows - 1);
+      const int cc = min(max(c0 + c % RW, 0), d.cols - 1);
+      reg[c] = ext[size_t(r) * d.cols + cc];
+    }
+    __syncthreads();
+    const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
+    const float inv = 1.0f / float(d.Nt);
+    for (int e = it.begin + tid; e < it.end; e += T) {
+      const int pid = d.ipts[e];
+      const int ang = pid / d.H, j = pid - ang * d.H;
+      int g0x, g0y;
+      float wx[W], wy[W];
+      point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+      const float2* p = reg + (g0x + rb) * RW + (g0y + cb);
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+          const float2 v = p[i * RW + l];
+          r.x = fmaf(wy[l], v.x, r.x);
+          r.y = fmaf(wy[l], v.y, r.y);
+        }
+        acc.x = fmaf(wx[i], r.x, acc.x);
+        acc.y = fmaf(wx[i], r.y, acc.y);
+      }
+      if (d.flip[ang]) acc.y = -acc.y;
+      d.yh[pid] = c_scale(acc, inv);
+    }
+  }
+}
+
+// F4 after k_interp_tiles: per pair of angles, the Hermitian completions of
+// the two half-lines packed as Z = X + iY, the inverse DFT along the line and
+// the real sinogram rows.
+template <int L>
+__global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
+  constexpr int T = fft_threads(L);
+  constexpr int H = L / 2 + 1;
+  __shared__ float2 sbuf[lds_elems<L>()];
+  const Lds s{sbuf};
+  const int tid = threadIdx.x;
+  NR_FOR_EACH_UNIT(a, wi) {
+    const DSlice d = load_desc(a.descs + wi.slice);
+    const int a0 = 2 * wi.unit, a1 = a0 + 1;
+    const bool has1 = a1 < d.na;
+    const NR_G float2* __restrict__ x0 = d.yh + size_t(a0) * H;
+    const NR_G float2* __restrict__ x1 = has1 ? x0 + H : x0;   // loads stay unconditional
+    NR_STRIDED(j, H, T) {
+      float2 X = x0[j], Y = x1[j];
+      if (!has1) Y = make_float2(0.f, 0.f);
+      if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
+        X.y = 0.f;
+        Y.y = 0.f;
+      }
+      s[j] = make_float2(X.x - Y.y, X.y + Y.x);
+      if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
+    }
+    __syncthreads();
+    fft_lds<L, T, true>(s, d.tw_Nt, tid);
+    float* __restrict__ o0 = a.sino_out + d.sino_off + size_t(a0) * L;
+    NR_STRIDED(m, L, T) {
       const float2 z = s[wrap_index<L>(m + L / 2)];
       o0[m] = z.x;
       if (has1) o0[L + m] = z.y;
@@ -258,18 +397,21 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(LaunchArgs a) {
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
+    const DSlice d = load_desc(a.descs + wi.slice);
     const int a0 = 2 * wi.unit, a1 = a0 + 1;
     const bool has1 = a1 < d.na;
     const float* __restrict__ y0 = a.sino_in + d.sino_off + size_t(a0) * L;
-    for (int m = tid; m < L; m += T)
-      s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? y0[L + m] : 0.f);
+    const float* __restrict__ y1 = has1 ? y0 + L : y0;   // loads stay unconditional
+    NR_STRIDED(m, L, T) {
+      const float b = y1[m];
+      s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? b : 0.f);
+    }
     __syncthreads();
-    fft_lds<L, T, false>(s, c2(d.tw_Nt), tid);
+    fft_lds<L, T, false>(s, d.tw_Nt, tid);
     const int H = L / 2 + 1;
-    float2* __restrict__ o0 = c2(d.yh) + size_t(a0) * H;
+    NR_G float2* __restrict__ o0 = d.yh + size_t(a0) * H;
     const float inv = 1.0f / float(L);
-    for (int j = tid; j < H; j += T) {
+    NR_STRIDED(j, H, T) {
       const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
       const float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
       o0[j] = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
@@ -292,10 +434,10 @@ __global__ void k_fill_zero(float4* p, size_t n4) {
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_spread_zero(LaunchArgs a) {
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
+    const DSlice d = load_desc(a.descs + wi.slice);
     const int t = d.zero_tiles[wi.unit];
     const int r0 = (t / d.tiles_x) * TH, c0 = (t % d.tiles_x) * TW;
-    float2* ext = c2(d.ext);
+    NR_G float2* ext = d.ext;
     for (int c = threadIdx.x; c < TW * TH; c += 256) {
       const int r = r0 + c / TW, cc = c0 + c % TW;
       if (r < d.rows && cc < d.cols) ext[size_t(r) * d.cols + cc] = make_float2(0.f, 0.f);
@@ -323,9 +465,9 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
   __shared__ int nonfinite;
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
+    const DSlice d = load_desc(a.descs + wi.slice);
     const SpreadItem it = d.items[wi.unit];
-    const float2* __restrict__ yh = c2(d.yh);
+    const NR_G float2* __restrict__ yh = d.yh;
     for (int c = tid; c < TH * TS; c += 256) {
       acc_re[c] = 0;
       acc_im[c] = 0;
@@ -417,7 +559,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
     __syncthreads();
     const bool shared_tile = it.flags & kItemAtomic;
     const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
-    float2* ext = c2(d.ext);
+    NR_G float2* ext = d.ext;
     for (int c = tid; c < TH * TW; c += 256) {
       const int rl = c / TW, cl = c % TW;
       const int r = r0 + rl, cc = c0 + cl;
@@ -440,16 +582,16 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
 template <int W>
 __global__ __launch_bounds__(256) void k_spread_atomic(const SliceDesc* descs, int slice, int halo, int colpad,
                                                        KBArgs kb) {
-  const SliceDesc& d = descs[slice];
+  const DSlice d = load_desc(descs + slice);
   const int pid = blockIdx.x * 256 + threadIdx.x;
   if (pid >= d.na * d.H) return;
   const int ang = pid / d.H, j = pid - ang * d.H;
-  float2 v = c2(d.yh)[pid];
+  float2 v = d.yh[pid];
   if (d.flip[ang]) v.y = -v.y;
   int g0x, g0y;
   float wx[W], wy[W];
   point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
-  float2* p = c2(d.ext) + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
+  NR_G float2* p = d.ext + size_t(g0x + halo) * d.cols + (g0y + d.G / 2 + colpad);
   for (int i = 0; i < W; ++i)
     for (int l = 0; l < W; ++l) {
       atomicAdd(&p[size_t(i) * d.cols + l].x, wx[i] * wy[l] * v.x);
@@ -463,7 +605,7 @@ __global__ __launch_bounds__(256) void k_spread_atomic(const SliceDesc* descs, i
 
 // sum of a main cell and its periodic copy in the padded columns
 template <int L>
-__device__ __forceinline__ float2 load_folded(const float2* row, int colpad, int n) {
+__device__ __forceinline__ float2 load_folded(const NR_G float2* row, int colpad, int n) {
   const int p = wrap_index<L>(n + L / 2) + colpad;
   float2 v = row[p];
   if (p >= L) v = c_add(v, row[p - L]);
@@ -479,24 +621,31 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
   const int tid = threadIdx.x;
   const int halo = a.halo, colpad = a.colpad;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
+    const DSlice d = load_desc(a.descs + wi.slice);
     const int qx = wi.unit;
-    const int cols = d.cols, N = d.N;
-    const float2* ext = c2(d.ext);
-    const float2* row = ext + size_t(qx + halo) * cols;
-    const float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
-    const float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    for (int n = tid; n < L; n += T) {
-      float2 v = load_folded<L>(row, colpad, n);
-      const int nm = n == 0 ? 0 : L - n;
-      if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
-      if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
-      s[n] = v;
+    const int cols = d.cols;
+    constexpr int N = L / 2;   // G = 2N
+    const NR_G float2* ext = d.ext;
+    const NR_G float2* row = ext + size_t(qx + halo) * cols;
+    const NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+    const NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+    NR_STRIDED(n, L, T) s[n] = row[wrap_index<L>(n + L / 2) + colpad];
+    // the periodic copies (n within colpad of L/2) and, for the columns next to
+    // qx = 0 and G/2, the conjugate mirror rows; each thread revisits its own n
+    NR_STRIDED(n, L, T) {
+      const int p = wrap_index<L>(n + L / 2) + colpad;
+      if (m1 || m2 || p >= L || p < 2 * colpad) {
+        float2 v = load_folded<L>(row, colpad, n);
+        const int nm = n == 0 ? 0 : L - n;
+        if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+        if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+        s[n] = v;
+      }
     }
     __syncthreads();
-    fft_lds<L, T, true>(s, c2(d.tw_G), tid);
-    float2* __restrict__ out = c2(d.T) + size_t(qx) * N;
-    for (int iy = tid; iy < N; iy += T) out[iy] = s[wrap_index<L>(iy - N / 2)];
+    fft_lds<L, T, true>(s, d.tw_G, tid);
+    NR_G float2* __restrict__ out = d.T + size_t(qx) * N;
+    NR_STRIDED(iy, N, T) out[iy] = s[wrap_index<L>(iy - N / 2)];
     __syncthreads();
   }
 }
@@ -512,12 +661,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
   const Lds s{sbuf};
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
-    const SliceDesc& d = a.descs[wi.slice];
-    const int N = d.N;
+    const DSlice d = load_desc(a.descs + wi.slice);
+    constexpr int N = L / 2;   // G = 2N
     const int iy0 = 2 * wi.unit;
-    const float4* __restrict__ in = reinterpret_cast<const float4*>(d.T);
+    const NR_G float4* __restrict__ in = (const NR_G float4*)d.T;
     // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
-    for (int q = tid; q <= L / 2; q += T) {
+    NR_STRIDED(q, L / 2 + 1, T) {
       const float4 t = in[(size_t(q) * N + iy0) >> 1];
       float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
       if (q == 0 || q == L / 2) {
@@ -528,10 +677,10 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
       if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
     }
     __syncthreads();
-    fft_lds<L, T, true>(s, c2(d.tw_G), tid);
+    fft_lds<L, T, true>(s, d.tw_G, tid);
     const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
     float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
-    for (int ix = tid; ix < N; ix += T) {
+    NR_STRIDED(ix, N, T) {
       const float2 z = s[wrap_index<L>(ix - N / 2)];
       const float dx = d.deapod[ix];
       g0[ix] = dx * d0 * z.x;
@@ -602,12 +751,24 @@ hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArg
       }
       break;
     case StageKind::FwdInterp:
+      if (L == 0) {   // tiled interpolation (the radial pass is its own stage)
+        if (W == 6) return launch(k_interp_tiles<6>, 256, a.n_work, st, a, kb);
+        if (W == 7) return launch(k_interp_tiles<7>, 256, a.n_work, st, a, kb);
+        return launch(k_interp_tiles<8>, 256, a.n_work, st, a, kb);
+      }
       switch (L) {
 #define NR_CASE(l)                                                                          \
   case l:                                                                                   \
     if (W == 6) return launch(k_fwd_interp<l, 6>, fft_threads(l), a.n_work, st, a, kb);     \
     if (W == 7) return launch(k_fwd_interp<l, 7>, fft_threads(l), a.n_work, st, a, kb);     \
     return launch(k_fwd_interp<l, 8>, fft_threads(l), a.n_work, st, a, kb);
+        NR_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      break;
+    case StageKind::FwdRadial:
+      switch (L) {
+#define NR_CASE(l) case l: return launch(k_fwd_radial<l>, fft_threads(l), a.n_work, st, a);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
       }

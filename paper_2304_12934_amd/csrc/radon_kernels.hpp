@@ -25,7 +25,7 @@ struct KBArgs {
 };
 
 // The stage kernels (same order as nr::Stage).
-enum class StageKind : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero };
+enum class StageKind : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread, AdjCols, AdjRows, SpreadZero, FwdRadial };
 
 // One grid-stride launch of `stage` over its work list; L = FFT length of the
 // slices in the list (unused by the spreading stages).

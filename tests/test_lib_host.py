@@ -109,7 +109,7 @@ def test_plan_info_and_workspace(L):
     G, tiles, entries, items, degree, slots, batches, launches = list(info)
     assert G == 256 and degree == 9
     assert slots == 2 and batches == 1          # both small slices share one batch
-    assert launches == 3 + 5                     # forward 3, adjoint 4 + the tile clear
+    assert launches == 4 + 5                     # forward 4, adjoint 4 + the tile clear
     assert entries >= 90 * 64          # every point j >= 1 sits in at least one tile
     assert items >= tiles
     nbytes = ctypes.c_size_t()
@@ -127,4 +127,8 @@ def test_plan_info_and_workspace(L):
     assert L.nr_plan_tune(h, b"tile_w", 32) == _lib.NR_OK
     assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_OK
     assert L.nr_plan_tune(h, b"no_such_key", 1) == _lib.NR_INVALID_ARG
+    # direct interpolation: one forward launch fewer (interpolation and radial pass fused)
+    assert L.nr_plan_tune(h, b"interp_mode", 2) == _lib.NR_INVALID_ARG
+    assert L.nr_plan_tune(h, b"interp_mode", 1) == _lib.NR_OK
+    assert L.nr_plan_info(h, 0, info, 8) == _lib.NR_OK and info[7] == 2 * (3 + 5)   # two batches
     L.nr_plan_destroy(h)
