@@ -110,7 +110,8 @@ nr_status nr_plan_destroy(nr_plan* plan);
 /* Set an execution parameter of a plan; none changes results beyond float32
  * rounding of the spreading sums.  Keys:
  *   "tile_w", "tile_h"  spreading tile (64x32 default; 32x32, 64x64, 128x32)
- *   "chunk"             most points per spreading or interpolation work item
+ *   "chunk"             most points per spreading or interpolation work item,
+ *                       64..1024
  *                       (1024 default)
  *   "interp_mode"       0 = interpolation from LDS-staged grid tiles (every
  *                       point once, by the tile of its first tap) followed by

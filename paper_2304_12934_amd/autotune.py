@@ -23,7 +23,7 @@ import torch
 from .radon import Plan, SliceGeometry
 
 TILES = [(64, 32), (32, 32), (64, 64), (128, 32)]
-CHUNKS = [512, 1024, 2048]
+CHUNKS = [256, 512, 1024]
 BUDGETS_MB = [1, 160, 640, 2048]     # 1 MiB: every slice runs alone
 DEFAULTS = {"tile_w": 64, "tile_h": 32, "chunk": 1024, "batch_mb": 160}
 

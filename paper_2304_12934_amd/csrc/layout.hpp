@@ -19,6 +19,10 @@ enum { kItemAtomic = 1, kItemDC = 2 };
 // SpreadItem with flags = bound = 0.
 constexpr int kInterpTileW = 64, kInterpTileH = 32;
 
+// Most points per spreading or interpolation work item (the kernels keep an
+// item's points in registers, kMaxChunk / 256 per thread).
+constexpr int kMaxChunk = 1024;
+
 // One slice as the kernels see it (device resident, filled at bind time).
 // Complex buffers are float pairs.
 struct SliceDesc {

@@ -427,8 +427,8 @@ nr_status layout_plan(Plan& plan, std::string& err) {
           " is not built (64x32, 32x32, 64x64, 128x32)";
     return NR_UNSUPPORTED_SIZE;
   }
-  if (tu.chunk < 64 || tu.chunk > 1 << 16) {
-    err = "chunk must be in [64, 65536]";
+  if (tu.chunk < 64 || tu.chunk > kMaxChunk) {
+    err = "chunk must be in [64, " + std::to_string(kMaxChunk) + "]";
     return NR_INVALID_ARG;
   }
   for (Geom& g : plan.geoms) {

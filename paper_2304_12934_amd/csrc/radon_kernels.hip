@@ -134,6 +134,43 @@ __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
   return x < 0 ? x + L : (x >= L ? x - L : x);
 }
 
+// Workgroup reductions of one float per thread (T threads, T/64 wavefronts):
+// butterfly within each wavefront, then the per-wavefront results through
+// `red` (T/64 floats of LDS).  Every thread gets the result; both contain a
+// barrier.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+template <int T>
+__device__ __forceinline__ float block_sum(float x, float* red) {
+  x = wave_sum(x);
+  __syncthreads();   // red may still be read from a previous reduction
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  float r = 0.f;
+#pragma unroll
+  for (int w = 0; w < T / 64; ++w) r += red[w];
+  return r;
+}
+template <int T>
+__device__ __forceinline__ float block_max(float x, float* red) {
+  x = wave_max(x);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  float r = 0.f;
+#pragma unroll
+  for (int w = 0; w < T / 64; ++w) r = fmaxf(r, red[w]);
+  return r;
+}
+
 // for (int n = tid; n < COUNT; n += T) with a compile-time trip count, so
 // that the compiler unrolls it and issues all of its loads before waiting
 #define NR_STRIDED(n, COUNT, T)                                                                       \
@@ -305,12 +342,29 @@ template <int W>
 __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
   constexpr int TW = kInterpTileW, TH = kInterpTileH;
   constexpr int RW = TW + W + 1, RH = TH + W + 1;
+  constexpr int T = 256, PER = kMaxChunk / T;
   __shared__ float2 reg[RH * RW];
   const int tid = threadIdx.x;
-  constexpr int T = 256;
   NR_FOR_EACH_UNIT(a, wi) {
     const DSlice d = load_desc(a.descs + wi.slice);
     const SpreadItem it = d.iitems[wi.unit];
+    // the thread's points and their angle tables, loaded up front (slots past
+    // the item's end repeat its first point; items are never empty),
+    // overlapping the tile staging
+    int pids[PER], fl[PER];
+    double gx[PER], gy[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * T;
+      pids[k] = d.ipts[it.begin + (e < it.end - it.begin ? e : 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int ang = pids[k] / d.H;
+      gx[k] = d.gxy[2 * ang];
+      gy[k] = d.gxy[2 * ang + 1];
+      fl[k] = d.flip[ang];
+    }
     const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 1;
     const NR_G float2* __restrict__ ext = d.ext;
     // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
@@ -322,12 +376,16 @@ __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
     __syncthreads();
     const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
     const float inv = 1.0f / float(d.Nt);
-    for (int e = it.begin + tid; e < it.end; e += T) {
-      const int pid = d.ipts[e];
+    const int count = it.end - it.begin;   // at most kMaxChunk
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (k * T >= count) break;          // uniform over the workgroup
+      if (tid + k * T >= count) continue;
+      const int pid = pids[k];
       const int ang = pid / d.H, j = pid - ang * d.H;
       int g0x, g0y;
       float wx[W], wy[W];
-      point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+      point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
       const float2* p = reg + (g0x + rb) * RW + (g0y + cb);
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
@@ -342,7 +400,7 @@ __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
         acc.x = fmaf(wx[i], r.x, acc.x);
         acc.y = fmaf(wx[i], r.y, acc.y);
       }
-      if (d.flip[ang]) acc.y = -acc.y;
+      if (fl[k]) acc.y = -acc.y;
       d.yh[pid] = c_scale(acc, inv);
     }
   }
@@ -459,16 +517,39 @@ template <int W, int TW, int TH>
 __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
   // row stride TW + 1: lanes stepping along a tile column hit different banks
   constexpr int TS = TW + 1;
+  constexpr int T = 256, PER = kMaxChunk / T;
   __shared__ int acc_re[TH * TS];
   __shared__ int acc_im[TH * TS];
-  __shared__ float red[256];
+  __shared__ float red[T / 64];
   __shared__ int nonfinite;
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
     const DSlice d = load_desc(a.descs + wi.slice);
     const SpreadItem it = d.items[wi.unit];
+    const int count = it.end - it.begin;   // at most kMaxChunk
     const NR_G float2* __restrict__ yh = d.yh;
-    for (int c = tid; c < TH * TS; c += 256) {
+    // the thread's points: ids, values and angle tables, every load issued up
+    // front and kept in registers.  Slots past the item's end repeat its first
+    // point; an empty item (a tile no point touches, which still writes its
+    // zeros) reads no point list at all and uses point 0.
+    int pid[PER];
+    float2 v[PER];
+    double gx[PER], gy[PER];
+    int fl[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * T;
+      pid[k] = count > 0 ? d.pts[it.begin + (e < count ? e : 0)] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int ang = pid[k] / d.H;
+      v[k] = yh[pid[k]];
+      gx[k] = d.gxy[2 * ang];
+      gy[k] = d.gxy[2 * ang + 1];
+      fl[k] = d.flip[ang];
+    }
+    for (int c = tid; c < TH * TS; c += T) {
       acc_re[c] = 0;
       acc_im[c] = 0;
     }
@@ -478,34 +559,23 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
     float dc = 0.f;
     if (it.flags & kItemDC) {
       float sum = 0.f;
-      for (int ang = tid; ang < d.na; ang += 256) sum += yh[size_t(ang) * d.H].x;
-      red[tid] = sum;
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-      }
-      dc = red[0];
-      __syncthreads();
+      for (int ang = tid; ang < d.na; ang += T) sum += yh[size_t(ang) * d.H].x;
+      dc = block_sum<T>(sum, red);
     }
     // fixed-point scale of this item; a non-finite value (which the integer
     // conversion would turn into 0) poisons the whole tile with NaN instead
-    if (tid == 0) nonfinite = !isfinite(dc);
     float m = 0.f;
-    bool bad = false;
-    for (int e = it.begin + tid; e < it.end; e += 256) {
-      const float2 v = yh[d.pts[e]];
-      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
-      bad |= !isfinite(v.x) || !isfinite(v.y);
+    bool bad = !isfinite(dc);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (tid + k * T < count) {
+        m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+        bad |= !isfinite(v[k].x) || !isfinite(v[k].y);
+      }
     }
-    red[tid] = m;
-    __syncthreads();
+    if (tid == 0) nonfinite = 0;
+    const float mmax = fmaxf(block_max<T>(m, red), fabsf(dc));   // synchronises: the tile is cleared
     if (bad) nonfinite = 1;
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
-      __syncthreads();
-    }
-    const float mmax = fmaxf(red[0], fabsf(dc));
     const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
     if ((it.flags & kItemDC) && tid < W * W) {
       int g0x, g0y;
@@ -516,16 +586,18 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
       if (rr >= 0 && rr < TH && cc >= 0 && cc < TW)
         atomicAdd(&acc_re[rr * TS + cc], __float2int_rn(q * dc * wx[i] * wy[l]));
     }
-    for (int e = it.begin + tid; e < it.end; e += 256) {
-      const int pid = d.pts[e];
-      const int ang = pid / d.H, j = pid - ang * d.H;
-      float2 v = yh[pid];
-      if (d.flip[ang]) v.y = -v.y;
-      v.x *= q;
-      v.y *= q;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (k * T >= count) break;          // uniform over the workgroup
+      if (tid + k * T >= count) continue;
+      const int ang = pid[k] / d.H, j = pid[k] - ang * d.H;
+      float2 u = v[k];
+      if (fl[k]) u.y = -u.y;
+      u.x *= q;
+      u.y *= q;
       int g0x, g0y;
       float wx[W], wy[W];
-      point_taps<W>(d.gxy[2 * ang], d.gxy[2 * ang + 1], j, kb, g0x, g0y, wx, wy);
+      point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
       const int rr0 = g0x + rbase, cc0 = g0y + cbase;
       if (rr0 >= 0 && rr0 + W <= TH && cc0 >= 0 && cc0 + W <= TW) {
         // whole footprint inside the tile
@@ -533,7 +605,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
         int* pim = acc_im + rr0 * TS + cc0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-          const float vx = wx[i] * v.x, vy = wx[i] * v.y;
+          const float vx = wx[i] * u.x, vy = wx[i] * u.y;
 #pragma unroll
           for (int l = 0; l < W; ++l) {
             atomicAdd(pre + i * TS + l, __float2int_rn(vx * wy[l]));
@@ -546,7 +618,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
       for (int i = 0; i < W; ++i) {
         const int rr = rr0 + i;
         if (rr < 0 || rr >= TH) continue;
-        const float vx = wx[i] * v.x, vy = wx[i] * v.y;
+        const float vx = wx[i] * u.x, vy = wx[i] * u.y;
 #pragma unroll
         for (int l = 0; l < W; ++l) {
           const int cc = cc0 + l;
@@ -560,15 +632,15 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
     const bool shared_tile = it.flags & kItemAtomic;
     const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
     NR_G float2* ext = d.ext;
-    for (int c = tid; c < TH * TW; c += 256) {
+    for (int c = tid; c < TH * TW; c += T) {
       const int rl = c / TW, cl = c % TW;
       const int r = r0 + rl, cc = c0 + cl;
       if (r >= d.rows || cc >= d.cols) continue;
-      float2* dst = ext + size_t(r) * d.cols + cc;
+      NR_G float2* dst = ext + size_t(r) * d.cols + cc;
       const float re = float(acc_re[rl * TS + cl]) * inv_q, im = float(acc_im[rl * TS + cl]) * inv_q;
       if (shared_tile) {
-        atomicAdd(&dst->x, re);
-        atomicAdd(&dst->y, im);
+        atomicAdd((float*)&dst->x, re);
+        atomicAdd((float*)&dst->y, im);
       } else {
         *dst = make_float2(re, im);
       }
