@@ -113,9 +113,15 @@ void KaiserBessel::init(int width, double beta_in) {
   // coefficients (a few 1e-8 of phi(0)) for the default shapes
   D = W + 2;
   coef.assign(size_t(W) * (D + 1), 0.0f);
-  for (int i = 0; i < W; ++i) {
+  // phi is even: tap W-1-i at z equals tap i at -z.  The upper taps take the
+  // lower taps' coefficients with the odd powers negated, exactly as the
+  // kernels evaluate them (in mirrored pairs).
+  for (int i = 0; i < (W + 1) / 2; ++i) {
     std::vector<double> m = fit_tap(*this, i, D);
-    for (int k = 0; k <= D; ++k) coef[size_t(i) * (D + 1) + k] = float(m[k]);
+    for (int k = 0; k <= D; ++k) {
+      coef[size_t(i) * (D + 1) + k] = float(m[k]);
+      coef[size_t(W - 1 - i) * (D + 1) + k] = (k % 2 ? -1.0f : 1.0f) * float(m[k]);
+    }
   }
 }
 

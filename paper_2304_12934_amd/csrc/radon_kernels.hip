@@ -69,16 +69,33 @@ __device__ __forceinline__ void point_taps(double gx, double gy, int j, const KB
   g0y = int(fy);
   const float zx = float(ux - fx - 0.5 * (W - 1));
   const float zy = float(uy - fy - 0.5 * (W - 1));
+  // phi is even, so tap W-1-i at z is tap i at -z: with p_i = E_i + O_i split
+  // into its even and odd powers, taps i and W-1-i are E_i(z) +- O_i(z), each
+  // part a Horner sum in z^2 (half the work of two full Horner sums)
+  const float tx = zx * zx, ty = zy * zy;
 #pragma unroll
-  for (int i = 0; i < W; ++i) {
-    float ax = kb.c[i * (D + 1) + D], ay = ax;
+  for (int i = 0; i < (W + 1) / 2; ++i) {
+    const float* c = kb.c + i * (D + 1);
+    constexpr int KE = (D / 2) * 2, KO = ((D - 1) / 2) * 2 + 1;   // highest even and odd powers
+    float ex = c[KE], ey = ex, ox = c[KO], oy = ox;
 #pragma unroll
-    for (int k = D - 1; k >= 0; --k) {
-      ax = fmaf(ax, zx, kb.c[i * (D + 1) + k]);
-      ay = fmaf(ay, zy, kb.c[i * (D + 1) + k]);
+    for (int k = KE - 2; k >= 0; k -= 2) {
+      ex = fmaf(ex, tx, c[k]);
+      ey = fmaf(ey, ty, c[k]);
     }
-    wx[i] = ax;
-    wy[i] = ay;
+#pragma unroll
+    for (int k = KO - 2; k >= 1; k -= 2) {
+      ox = fmaf(ox, tx, c[k]);
+      oy = fmaf(oy, ty, c[k]);
+    }
+    ox *= zx;
+    oy *= zy;
+    wx[i] = ex + ox;
+    wy[i] = ey + oy;
+    if (W - 1 - i != i) {
+      wx[W - 1 - i] = ex - ox;
+      wy[W - 1 - i] = ey - oy;
+    }
   }
 }
 
