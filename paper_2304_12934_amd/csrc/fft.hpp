@@ -270,7 +270,12 @@ __device__ __forceinline__ void fft_lds(Lds s, TwPtr __restrict__ tw, int tid) {
   fft_passes<L, T, INV>(s, tw, tid);
 }
 
-// threads per transform for a length-L FFT
-constexpr int fft_threads(int L) { return L >= 2048 ? 256 : (L >= 512 ? 128 : 64); }
+// threads per transform for a length-L FFT.  For 5·2^a lengths five
+// wavefronts split the radix-8 and radix-4 passes evenly (2560: 320 radix-8
+// butterflies per pass; 5120: 640 and 1280), where four would leave the last
+// round of each pass partly idle.
+constexpr int fft_threads(int L) {
+  return (L == 2560 || L == 5120) ? 320 : (L >= 2048 ? 256 : (L >= 512 ? 128 : 64));
+}
 
 }  // namespace nrk
