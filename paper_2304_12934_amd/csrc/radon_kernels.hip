@@ -355,12 +355,18 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
 // W-1 cells the footprints reach past it and a one-cell margin on each side,
 // then every thread interpolates its points from LDS (the same sums, in the
 // same order, as interp_point) into the half-line buffer yh, scaled by 1/N_t.
+// The staged cells are split into a real and an imaginary plane with an odd
+// row stride: neighbouring lanes take neighbouring points of one line, about
+// two cells apart, and an even stride (interleaved complex values) put them
+// on a few LDS banks.
 template <int W>
 __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
   constexpr int TW = kInterpTileW, TH = kInterpTileH;
   constexpr int RW = TW + W + 1, RH = TH + W + 1;
+  constexpr int RS = RW | 1;   // odd row stride of the planes
   constexpr int T = 256, PER = kMaxChunk / T;
-  __shared__ float2 reg[RH * RW];
+  __shared__ float reg_re[RH * RS];
+  __shared__ float reg_im[RH * RS];
   const int tid = threadIdx.x;
   NR_FOR_EACH_UNIT(a, wi) {
     const DSlice d = load_desc(a.descs + wi.slice);
@@ -386,9 +392,12 @@ __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
     const NR_G float2* __restrict__ ext = d.ext;
     // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
     NR_STRIDED(c, RH * RW, T) {
-      const int r = min(max(r0 + c / RW, 0), d.rows - 1);
-      const int cc = min(max(c0 + c % RW, 0), d.cols - 1);
-      reg[c] = ext[size_t(r) * d.cols + cc];
+      const int rl = c / RW, cl = c % RW;
+      const int r = min(max(r0 + rl, 0), d.rows - 1);
+      const int cc = min(max(c0 + cl, 0), d.cols - 1);
+      const float2 v = ext[size_t(r) * d.cols + cc];
+      reg_re[rl * RS + cl] = v.x;
+      reg_im[rl * RS + cl] = v.y;
     }
     __syncthreads();
     const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
@@ -403,14 +412,14 @@ __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
       int g0x, g0y;
       float wx[W], wy[W];
       point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
-      const float2* p = reg + (g0x + rb) * RW + (g0y + cb);
+      const int o = (g0x + rb) * RS + (g0y + cb);
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int i = 0; i < W; ++i) {
         float2 r = make_float2(0.f, 0.f);
 #pragma unroll
         for (int l = 0; l < W; ++l) {
-          const float2 v = p[i * RW + l];
+          const float2 v = make_float2(reg_re[o + i * RS + l], reg_im[o + i * RS + l]);
           r.x = fmaf(wy[l], v.x, r.x);
           r.y = fmaf(wy[l], v.y, r.y);
         }
