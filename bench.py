@@ -249,6 +249,9 @@ def main() -> int:
     ap.add_argument("--mbir-slices", type=int, default=64)
     ap.add_argument("--mbir-angles", type=int, default=256)
     ap.add_argument("--mbir-iters", type=int, default=50)
+    ap.add_argument("--tile-w", type=int, default=None, help="spreading tile width (plan tuning)")
+    ap.add_argument("--tile-h", type=int, default=None, help="spreading tile height (plan tuning)")
+    ap.add_argument("--chunk", type=int, default=None, help="points per spreading/interpolation item")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of MIB MiB before timing (a counter reference)")
     args = ap.parse_args()
@@ -286,7 +289,9 @@ def main() -> int:
         print(f"[bench] calibration copy of {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
         del src, dst
 
-    plan = Plan.uniform_stack(n, nd, angles, S, device=dev)
+    tuning = {k: v for k, v in (("tile_w", args.tile_w), ("tile_h", args.tile_h), ("chunk", args.chunk))
+              if v is not None}
+    plan = Plan.uniform_stack(n, nd, angles, S, device=dev, tuning=tuning or None)
     info = plan.info(0)
     sino = torch.empty(plan.sino_shape(), dtype=torch.float32, device=dev)
     back = torch.empty(plan.vol_shape(), dtype=torch.float32, device=dev)
@@ -396,7 +401,7 @@ def main() -> int:
         "config": {"workload": f"{S} slices {n}x{n} random ellipses ({args.ellipses} each), {na} angles in [0,pi), "
                                f"{nd} bins, forward+adjoint per slice",
                    "slices": S, "n": n, "n_angles": na, "n_det": nd, "kernel_width": 7, "oversampling": 2,
-                   "parallelism": "none (1 GPU)"},
+                   "parallelism": "none (1 GPU)", **({"tuning": tuning} if tuning else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "model_bytes_per_slice": int(mb),

@@ -5,7 +5,8 @@
 // pass loads every butterfly input of the thread into registers, waits at a
 // barrier, then writes its outputs back over the same LDS buffer, so one
 // L-point buffer is enough.  Radices: 8, 4, 2 for the power-of-two part
-// (as many 8s as possible, the remainder as 4s), then 5 and 3.  Twiddles
+// (as many 8s as possible, the remainder as 4s), then 5 and 3; 4096 and 5120
+// take three passes of radix 16 (16, 20).  Twiddles
 // come from a table of exp(-2 pi i m/L), m < L, computed in float64 on the
 // host and rounded once to float32.
 #pragma once
@@ -51,6 +52,11 @@ constexpr int pow2_exponent(int v) {
 }
 
 constexpr int radix_of(int L, int p) {
+  // three passes for the two longest transforms of the 2560^2 and 2048^2
+  // workloads: radix 16 and 20 butterflies in registers, one LDS round trip
+  // per pass
+  if (L == 5120) return p == 0 ? 16 : (p == 1 ? 16 : (p == 2 ? 20 : 1));
+  if (L == 4096) return p < 3 ? 16 : 1;
   int r[24] = {};
   int n = 0;
   const int e = pow2_exponent(L);
@@ -182,6 +188,82 @@ struct Dft<5, INV> {
     v[3] = c_sub(t2, u2);
   }
 };
+
+// cos and sin of 2 pi m / N for the composite butterflies below
+template <int N>
+struct UnitRoots;
+template <>
+struct UnitRoots<16> {
+  static constexpr float c[16] = {1.f, 0.92387953251128674f, 0.70710678118654757f, 0.38268343236508984f,
+                                  0.f, -0.38268343236508984f, -0.70710678118654757f, -0.92387953251128674f,
+                                  -1.f, -0.92387953251128674f, -0.70710678118654757f, -0.38268343236508984f,
+                                  0.f, 0.38268343236508984f, 0.70710678118654757f, 0.92387953251128674f};
+  static constexpr float s[16] = {0.f, 0.38268343236508984f, 0.70710678118654757f, 0.92387953251128674f,
+                                  1.f, 0.92387953251128674f, 0.70710678118654757f, 0.38268343236508984f,
+                                  0.f, -0.38268343236508984f, -0.70710678118654757f, -0.92387953251128674f,
+                                  -1.f, -0.92387953251128674f, -0.70710678118654757f, -0.38268343236508984f};
+};
+template <>
+struct UnitRoots<20> {
+  static constexpr float c[20] = {1.f, 0.95105651629515357f, 0.80901699437494742f, 0.58778525229247313f,
+                                  0.30901699437494742f, 0.f, -0.30901699437494742f, -0.58778525229247313f,
+                                  -0.80901699437494742f, -0.95105651629515357f, -1.f, -0.95105651629515357f,
+                                  -0.80901699437494742f, -0.58778525229247313f, -0.30901699437494742f, 0.f,
+                                  0.30901699437494742f, 0.58778525229247313f, 0.80901699437494742f,
+                                  0.95105651629515357f};
+  static constexpr float s[20] = {0.f, 0.30901699437494742f, 0.58778525229247313f, 0.80901699437494742f,
+                                  0.95105651629515357f, 1.f, 0.95105651629515357f, 0.80901699437494742f,
+                                  0.58778525229247313f, 0.30901699437494742f, 0.f, -0.30901699437494742f,
+                                  -0.58778525229247313f, -0.80901699437494742f, -0.95105651629515357f, -1.f,
+                                  -0.95105651629515357f, -0.80901699437494742f, -0.58778525229247313f,
+                                  -0.30901699437494742f};
+};
+
+// a * exp(-+2 pi i m/N) for an index m that is a constant once the calling
+// loops are unrolled (the quarter turns are sign swaps)
+template <int N, bool INV>
+__device__ __forceinline__ float2 mul_root(float2 a, int m) {
+  m %= N;
+  if (m == 0) return a;
+  if (4 * m == N) return mul_i<INV>(a);
+  if (2 * m == N) return make_float2(-a.x, -a.y);
+  if (4 * m == 3 * N) return mul_i<!INV>(a);
+  const float c = UnitRoots<N>::c[m], sn = INV ? UnitRoots<N>::s[m] : -UnitRoots<N>::s[m];
+  return make_float2(a.x * c - a.y * sn, a.x * sn + a.y * c);
+}
+
+// N = P*Q point DFT from P- and Q-point ones: input n = Q*n1 + n2, output
+// k = k1 + P*k2; DFT_P over n1 for each n2, twiddles W_N^(n2*k1), DFT_Q over
+// n2 for each k1.
+template <int P, int Q, bool INV>
+struct DftPQ {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 y[Q][P];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      float2 t[P];
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) t[n1] = v[Q * n1 + n2];
+      Dft<P, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) y[n2][k1] = mul_root<P * Q, INV>(t[k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      float2 t[Q];
+#pragma unroll
+      for (int n2 = 0; n2 < Q; ++n2) t[n2] = y[n2][k1];
+      Dft<Q, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = t[k2];
+    }
+  }
+};
+
+template <bool INV>
+struct Dft<16, INV> : DftPQ<4, 4, INV> {};
+template <bool INV>
+struct Dft<20, INV> : DftPQ<5, 4, INV> {};
 
 // ---------------------------------------------------------------------------
 // LDS buffer of one transform (unpadded: measured faster than a padded

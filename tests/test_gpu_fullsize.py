@@ -60,3 +60,26 @@ def test_adjoint_sampled_angles(setup):
     e = rel(g, ref)
     print(f"adj rel L2 (y on {len(SAMPLE)} angles): {e:.3e}", flush=True)
     assert e < TOL
+
+
+def test_2048_forward_and_adjoint_sampled():
+    """2048^2 slices (4096-point grid transforms), 512 angles, sampled against the oracle."""
+    from paper_2304_12934_amd import Plan
+    print("case: 2048^2, 512 angles, sampled fwd/adj", flush=True)
+    dev = torch.device("cuda", 0)
+    n, na = 2048, 512
+    ang = synth.uniform_angles(na)
+    f = synth.ellipse_phantom(2, 1, n, 20).numpy()
+    plan = Plan.uniform_stack(n, n, ang, 1, device=dev)
+    sample = np.array([0, 129, 300, 511])
+    s = plan.fwd(torch.as_tensor(f[None], dtype=torch.float32, device=dev)).cpu().numpy()[0]
+    e = rel(s[sample], ora.radon_fwd(f, ang[sample], n))
+    print(f"2048 fwd rel L2: {e:.3e}", flush=True)
+    assert e < TOL
+    rng = np.random.default_rng(8)
+    y = np.zeros((na, n))
+    y[sample] = rng.standard_normal((len(sample), n))
+    g = plan.adj(torch.as_tensor(y[None], dtype=torch.float32, device=dev)).cpu().numpy()[0]
+    e = rel(g, ora.radon_adj(y[sample], ang[sample], n))
+    print(f"2048 adj rel L2: {e:.3e}", flush=True)
+    assert e < TOL
