@@ -632,6 +632,9 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.items = reinterpret_cast<const SpreadItem*>(d_ws + g.off_items);
       d.zero_tiles = reinterpret_cast<const int32_t*>(d_ws + g.off_zero);
       d.itiles_x = g.itiles_x;
+      // the polar points reach |u| = (N_t/2)(G/N_t) = G/2 cells; their taps
+      // W/2 cells further (one cell of margin on top)
+      d.rdisc = g.G / 2 + (plan.kb.W + 1) / 2 + 2;
       d.ipts = reinterpret_cast<const int32_t*>(d_ws + g.off_ipts);
       d.iitems = reinterpret_cast<const SpreadItem*>(d_ws + g.off_iitems);
       out[size_t(s)] = d;

@@ -119,7 +119,7 @@ struct DSlice {
   const NR_G int32_t* zero_tiles;
   const NR_G int32_t* ipts;
   const NR_G SpreadItem* iitems;
-  int itiles_x;
+  int itiles_x, rdisc;
 };
 
 // The slice descriptor by value (uniform: scalar loads).
@@ -143,6 +143,7 @@ __device__ __forceinline__ DSlice load_desc(const SliceDesc* p) {
   d.ipts = (const NR_G int32_t*)s.ipts;
   d.iitems = (const NR_G SpreadItem*)s.iitems;
   d.itiles_x = s.itiles_x;
+  d.rdisc = s.rdisc;
   return d;
 }
 
@@ -274,7 +275,15 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
     // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
     NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
     NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    NR_STRIDED(n, L, T) {
+    // only |q| <= rdisc is ever read: the natural indices n in [0, lim] and
+    // [L - lim, L) of this row (a cell's periodic copies lie farther out than
+    // the cell itself, and mirror rows keep |q_y|)
+    const int r2 = d.rdisc * d.rdisc - qx * qx;
+    const int lim = r2 <= 0 ? -1 : int(sqrtf(float(r2)));
+    const bool full = lim >= L / 2;   // the whole row, q_y = -L/2 included
+    const int cnt = full ? L : 2 * lim + 1;
+    for (int k = tid; k < cnt; k += T) {
+      const int n = (full || k <= lim) ? k : L - cnt + k;
       const float2 v = s[n];
       store_row<L>(row, colpad, n, v);
       const int nm = n == 0 ? 0 : L - n;
