@@ -252,6 +252,8 @@ def main() -> int:
     ap.add_argument("--tile-w", type=int, default=None, help="spreading tile width (plan tuning)")
     ap.add_argument("--tile-h", type=int, default=None, help="spreading tile height (plan tuning)")
     ap.add_argument("--chunk", type=int, default=None, help="points per spreading/interpolation item")
+    ap.add_argument("--streams", type=int, default=None, help="concurrent streams of the plan (plan tuning)")
+    ap.add_argument("--batch-mb", type=int, default=None, help="scratch budget of one batch in MiB (plan tuning)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of MIB MiB before timing (a counter reference)")
     args = ap.parse_args()
@@ -289,8 +291,8 @@ def main() -> int:
         print(f"[bench] calibration copy of {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
         del src, dst
 
-    tuning = {k: v for k, v in (("tile_w", args.tile_w), ("tile_h", args.tile_h), ("chunk", args.chunk))
-              if v is not None}
+    tuning = {k: v for k, v in (("tile_w", args.tile_w), ("tile_h", args.tile_h), ("chunk", args.chunk),
+                                ("streams", args.streams), ("batch_mb", args.batch_mb)) if v is not None}
     plan = Plan.uniform_stack(n, nd, angles, S, device=dev, tuning=tuning or None)
     info = plan.info(0)
     sino = torch.empty(plan.sino_shape(), dtype=torch.float32, device=dev)

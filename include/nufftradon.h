@@ -126,6 +126,11 @@ nr_status nr_plan_destroy(nr_plan* plan);
  *                       one 2560^2 slice, whose grids then stay in the 256 MB
  *                       last-level cache between stages; a slice larger than
  *                       the budget runs alone)
+ *   "streams"           1..8 (4 default): batches run round-robin on this many
+ *                       streams the plan owns (forked from and joined back to
+ *                       the caller's stream on every call), each with its own
+ *                       scratch, so that the stages of different batches
+ *                       overlap on the device
  *   "spread_mode"       0 = LDS-tiled spreading (default), 1 = one thread per
  *                       point with global float atomics (a slow cross-check)
  * Changing any key but spread_mode unbinds the plan: query

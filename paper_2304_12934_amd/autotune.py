@@ -1,7 +1,8 @@
 """Autotuner for the execution parameters of a plan.
 
 Times forward + adjoint passes of a stack on the device for candidate
-settings of the batch budget (``batch_mb``), the spreading tile shape
+settings of the batch budget (``batch_mb``), the number of concurrent
+streams (``streams``), the spreading tile shape
 (``tile_w`` x ``tile_h``) and the spreading item size (``chunk``), one
 parameter at a time (coordinate search from the defaults), and caches the
 best setting per geometry and device in a JSON file.  Every candidate
@@ -25,7 +26,8 @@ from .radon import Plan, SliceGeometry
 TILES = [(64, 32), (32, 32), (64, 64), (128, 32)]
 CHUNKS = [256, 512, 1024]
 BUDGETS_MB = [1, 160, 640, 2048]     # 1 MiB: every slice runs alone
-DEFAULTS = {"tile_w": 64, "tile_h": 32, "chunk": 1024, "batch_mb": 160}
+STREAMS = [1, 2, 4, 6]
+DEFAULTS = {"tile_w": 64, "tile_h": 32, "chunk": 1024, "batch_mb": 160, "streams": 4}
 
 
 def default_cache_path() -> str:
@@ -92,6 +94,9 @@ def autotune(geoms: Sequence[SliceGeometry], width: int = 7, device: torch.devic
     for mb in BUDGETS_MB:
         if mb != best["batch_mb"]:
             consider({**best, "batch_mb": mb})
+    for ns in STREAMS:
+        if ns != best["streams"]:
+            consider({**best, "streams": ns})
     for tw, th in TILES:
         if (tw, th) != (best["tile_w"], best["tile_h"]):
             consider({**best, "tile_w": tw, "tile_h": th})

@@ -31,12 +31,28 @@ struct nr_plan {
   std::vector<StageEvents> recorded;
   std::vector<hipEvent_t> pool;
   std::vector<SliceDesc> host_descs;
+  // concurrent lanes: streams (default priority, non-blocking) plus the
+  // events that fork them from and join them back to the caller's stream
+  int lane_device = -1;
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
+  void drop_lanes() {
+    for (hipStream_t l : lanes) (void)hipStreamDestroy(l);
+    for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    lanes.clear();
+    lane_done.clear();
+    fork = nullptr;
+    lane_device = -1;
+  }
   ~nr_plan() {
     for (auto& r : recorded) {
       (void)hipEventDestroy(r.start);
       (void)hipEventDestroy(r.stop);
     }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    drop_lanes();
   }
 };
 
@@ -126,10 +142,39 @@ int stage_event_id(nr::Stage s) {
   }
 }
 
-// Enqueue the stage launches of every batch (forward or adjoint chain).
+// The plan's lane streams on the current device (created on first use).
+hipError_t ensure_lanes(nr_plan* plan, int n) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (plan->lane_device != dev) plan->drop_lanes();
+  plan->lane_device = dev;
+  if (!plan->fork && (e = hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming)) != hipSuccess) return e;
+  while (int(plan->lanes.size()) < n) {
+    hipStream_t l = nullptr;
+    hipEvent_t ev = nullptr;
+    if ((e = hipStreamCreateWithFlags(&l, hipStreamNonBlocking)) != hipSuccess) return e;
+    plan->lanes.push_back(l);
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    plan->lane_done.push_back(ev);
+  }
+  return hipSuccess;
+}
+
+// Enqueue the stage launches of every batch (forward or adjoint chain).  With
+// several lanes the batches run round-robin on the lane streams, which first
+// wait for the work already on st; st then waits for every lane.
 nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol_out, const float* sino_in,
                     float* sino_out, hipStream_t st, const char* where) {
   const nr::Plan& p = plan->p;
+  const int nl = p.n_lanes;
+  if (nl > 1) {
+    hipError_t e = ensure_lanes(plan, nl);
+    if (e == hipSuccess) e = hipEventRecord(plan->fork, st);
+    for (int l = 0; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(plan->lanes[size_t(l)], plan->fork, 0);
+    if (e != hipSuccess) return hip_fail(e, where);
+  }
+  auto lane_stream = [&](const nr::Batch& bt) { return nl > 1 ? plan->lanes[size_t(bt.lane)] : st; };
   const nrk::KBArgs kb = kb_args(p);
   const char* base = static_cast<const char*>(p.d_ws);
   nrk::LaunchArgs a{};
@@ -141,6 +186,7 @@ nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol
   a.sino_in = sino_in;
   a.sino_out = sino_out;
   for (const nr::Batch& bt : p.batches) {
+    hipStream_t bs = lane_stream(bt);
     for (const nr::StageLaunch& sl : forward ? bt.fwd : bt.adj) {
       const bool spread = sl.stage == nr::Stage::Spread || sl.stage == nr::Stage::SpreadZero;
       hipError_t e = hipSuccess;
@@ -148,9 +194,9 @@ nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol
         // reference spreading, one slice at a time
         if (sl.stage == nr::Stage::SpreadZero) continue;
         for (int s : bt.slices) {
-          e = timed(plan, kStageSpread, st, [&] {
+          e = timed(plan, kStageSpread, bs, [&] {
             return nrk::launch_spread_reference(a.descs, s, plan->host_descs[size_t(s)], p.halo, p.colpad, kb,
-                                                p.kb.W, st);
+                                                p.kb.W, bs);
           });
           if (e != hipSuccess) break;
         }
@@ -158,13 +204,21 @@ nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol
         nrk::LaunchArgs la = a;
         la.work = reinterpret_cast<const WorkItem*>(base + p.off_work + sl.work_off);
         la.n_work = sl.n_work;
-        e = timed(plan, stage_event_id(sl.stage), st, [&] {
+        e = timed(plan, stage_event_id(sl.stage), bs, [&] {
           return nrk::launch_stage(static_cast<nrk::StageKind>(int(sl.stage)), sl.L, la, kb, p.kb.W,
-                                   p.tune.tile_w, p.tune.tile_h, st);
+                                   p.tune.tile_w, p.tune.tile_h, bs);
         });
       }
       if (e != hipSuccess) return hip_fail(e, where);
     }
+  }
+  if (nl > 1) {
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < nl && e == hipSuccess; ++l) {
+      e = hipEventRecord(plan->lane_done[size_t(l)], plan->lanes[size_t(l)]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->lane_done[size_t(l)], 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, where);
   }
   return NR_OK;
 }
@@ -336,6 +390,9 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
     t.tile_h = int(value);
   } else if (std::strcmp(key, "chunk") == 0) {
     t.chunk = int(value);
+  } else if (std::strcmp(key, "streams") == 0) {
+    if (value < 1 || value > 8) return fail(NR_INVALID_ARG, "streams must be in [1, 8]");
+    t.streams = int(value);
   } else if (std::strcmp(key, "interp_mode") == 0) {
     if (value != 0 && value != 1) return fail(NR_INVALID_ARG, "interp_mode must be 0 (tiles) or 1 (direct)");
     t.interp_mode = int(value);

@@ -459,6 +459,10 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     err = "batch and batch_mb must be >= 0";
     return NR_INVALID_ARG;
   }
+  if (tu.streams < 1 || tu.streams > 8) {
+    err = "streams must be in [1, 8]";
+    return NR_INVALID_ARG;
+  }
   // batches: consecutive slices while their scratch fits the budget (a slice
   // larger than the budget runs alone); a budget of one slot's size keeps each
   // slice's grids resident in the 256 MB last-level cache between stages
@@ -590,8 +594,11 @@ nr_status layout_plan(Plan& plan, std::string& err) {
   off = align_up(off + size_t(ns) * sizeof(SliceDesc), 256);
   plan.off_work = off;
   off = align_up(off + std::max<size_t>(1, plan.work.size()) * sizeof(WorkItem), 256);
+  // batches round-robin over the lanes; each lane has its own scratch area
+  plan.n_lanes = std::max(1, std::min(tu.streams, int(plan.batches.size())));
+  for (size_t b = 0; b < plan.batches.size(); ++b) plan.batches[b].lane = int(b % size_t(plan.n_lanes));
   plan.off_slot = off;
-  plan.ws_bytes = plan.off_slot + plan.slot_area;
+  plan.ws_bytes = plan.off_slot + size_t(plan.n_lanes) * plan.slot_area;
   plan.laid_out = true;
   return NR_OK;
 }
@@ -622,7 +629,7 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.tw_Nt = reinterpret_cast<const float*>(d_ws + plan.off_twiddle.at(sl.n_det));
       d.gxy = reinterpret_cast<const double*>(d_ws + g.off_gxy);
       d.flip = reinterpret_cast<const int32_t*>(d_ws + g.off_flip);
-      char* slot = d_ws + plan.off_slot + bt.slot_off[k];
+      char* slot = d_ws + plan.off_slot + size_t(bt.lane) * plan.slot_area + bt.slot_off[k];
       const size_t ext_off = align_up(size_t(g.G / 2 + 1) * g.key.n * sizeof(f2), 256);
       const size_t yh_off = align_up(ext_off + size_t(g.rows) * g.cols * sizeof(f2), 256);
       d.T = reinterpret_cast<float*>(slot);

@@ -88,6 +88,7 @@ struct Tuning {
   int batch_mb = 160;             // scratch budget of one batch in MiB (a lone slice may exceed it)
   int spread_mode = 0;            // 0: LDS tiles, 1: global atomics (reference)
   int interp_mode = 0;            // 0: LDS tiles + radial pass, 1: direct gathers per angle pair
+  int streams = 4;                // batches run round-robin on this many concurrent streams
 };
 
 // Stages of the forward chain (FwdRows, FwdCols, FwdInterp, FwdRadial) and of the
@@ -106,8 +107,9 @@ struct StageLaunch {
 };
 
 struct Batch {
+  int lane = 0;                   // stream (and scratch area) the batch runs on
   std::vector<int> slices;
-  std::vector<size_t> slot_off;   // scratch offset of each slice inside the slot area
+  std::vector<size_t> slot_off;   // scratch offset of each slice inside its lane's slot area
   std::vector<StageLaunch> fwd, adj;
 };
 
@@ -131,7 +133,8 @@ struct Plan {
   std::vector<Batch> batches;
   std::vector<WorkItem> work;       // every work list, concatenated
   size_t off_desc = 0, off_work = 0, off_slot = 0;
-  size_t slot_area = 0;             // bytes of the largest batch's scratch
+  size_t slot_area = 0;             // bytes of the largest batch's scratch (one area per lane)
+  int n_lanes = 1;                  // concurrent streams in use (at most the number of batches)
   int n_slots = 0;                  // most slices in one batch
   size_t ws_bytes = 0;
 

@@ -116,12 +116,20 @@ def test_plan_info_and_workspace(L):
     assert L.nr_plan_workspace_bytes(h, ctypes.byref(nbytes)) == _lib.NR_OK
     # at least the extended half-plane grid (G/2 + 1 + 8 rows of G + 8 complex)
     assert nbytes.value >= (G // 2 + 9) * (G + 8) * 8
-    # tuning: one slice per batch halves the scratch, an unknown tile is refused
+    # tuning: one slice per batch on one stream halves the scratch; on two
+    # streams each keeps its own scratch; an unknown tile is refused
+    assert L.nr_plan_tune(h, b"streams", 1) == _lib.NR_OK
     assert L.nr_plan_tune(h, b"batch", 1) == _lib.NR_OK
     small = ctypes.c_size_t()
     assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_OK
     assert small.value < nbytes.value
     assert L.nr_plan_info(h, 0, info, 8) == _lib.NR_OK and info[5] == 1 and info[6] == 2
+    assert L.nr_plan_tune(h, b"streams", 2) == _lib.NR_OK
+    lanes = ctypes.c_size_t()
+    assert L.nr_plan_workspace_bytes(h, ctypes.byref(lanes)) == _lib.NR_OK
+    assert lanes.value > small.value
+    assert L.nr_plan_tune(h, b"streams", 9) == _lib.NR_INVALID_ARG
+    assert L.nr_plan_tune(h, b"streams", 1) == _lib.NR_OK
     assert L.nr_plan_tune(h, b"tile_w", 48) == _lib.NR_OK
     assert L.nr_plan_workspace_bytes(h, ctypes.byref(small)) == _lib.NR_UNSUPPORTED_SIZE
     assert L.nr_plan_tune(h, b"tile_w", 32) == _lib.NR_OK
