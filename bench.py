@@ -299,8 +299,7 @@ def main() -> int:
     back = torch.empty(plan.vol_shape(), dtype=torch.float32, device=dev)
 
     def step():
-        plan.fwd(vol, sino)
-        plan.adj(sino, back)
+        plan.normal(vol, None, sino, back)   # sino = R vol, back = R^T sino
 
     for _ in range(args.warmup):
         step()

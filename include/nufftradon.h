@@ -138,8 +138,8 @@ nr_status nr_plan_destroy(nr_plan* plan);
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
 
 /* Stage timing for measurement.  While enabled, every stage launch of
- * radon_fwd / radon_adj / mbir_step is bracketed by two HIP events on the
- * caller's stream.  nr_plan_profile_read waits for the last recorded event
+ * radon_fwd / radon_adj / radon_normal / mbir_step is bracketed by two HIP
+ * events on the stream it runs on (the caller's or one of the plan's).  nr_plan_profile_read waits for the last recorded event
  * and returns, per stage, the summed milliseconds and the launch count, then
  * forgets the records.  Stages: 0 forward rows, 1 forward columns, 2
  * interpolation + radial transform, 3 adjoint radial transform, 4 spreading,
@@ -156,6 +156,16 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
  * of radon_fwd).  d_sino: float32 input; d_vol: float32 output,
  * overwritten.  Device pointers. */
 nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream);
+
+/* The gradient of the data term (Sec. 3, eq. "gradient"): d_sino = R f - b
+ * (R f when d_b is NULL) and d_vol_out = R^T d_sino, for every slice.  Same
+ * values as radon_fwd, the subtraction and radon_adj in sequence; each batch
+ * of slices runs its forward, residual and adjoint back to back on one of
+ * the plan's streams, with no wait for the other batches in between.
+ * d_vol, d_b, d_sino, d_vol_out: float32 device buffers in the plan's layout
+ * (d_sino and d_vol_out overwritten; d_vol_out must not alias d_vol). */
+nr_status radon_normal(nr_plan* plan, const float* d_vol, const float* d_b, float* d_sino, float* d_vol_out,
+                       nr_stream stream);
 
 /* Data term of the objective (Sec. 3, eq. "objfn" with G = 1/2 ||R f - b||^2):
  * d_r = R f - b (sinogram layout, overwritten) and, when d_value is not NULL,

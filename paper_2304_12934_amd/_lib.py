@@ -62,6 +62,7 @@ SIGNATURES = {
     "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "radon_normal": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,
                               c_void_p]),
     "mbir_step": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,

@@ -161,11 +161,14 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
   return hipSuccess;
 }
 
-// Enqueue the stage launches of every batch (forward or adjoint chain).  With
-// several lanes the batches run round-robin on the lane streams, which first
-// wait for the work already on st; st then waits for every lane.
-nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol_out, const float* sino_in,
-                    float* sino_out, hipStream_t st, const char* where) {
+// Enqueue, for every batch, the forward chain (vol_in -> sino_out), then the
+// residual sino_out -= b of its slices (b not null), then the adjoint chain
+// (sino_in -> vol_out), as asked.  With several lanes the batches run
+// round-robin on the lane streams, which first wait for the work already on
+// st; st then waits for every lane.  Each batch's adjoint follows its own
+// forward on its lane, with no join in between.
+nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const float* vol_in, float* vol_out,
+                      const float* sino_in, float* sino_out, hipStream_t st, const char* where) {
   const nr::Plan& p = plan->p;
   const int nl = p.n_lanes;
   if (nl > 1) {
@@ -187,7 +190,24 @@ nr_status run_chain(nr_plan* plan, bool forward, const float* vol_in, float* vol
   a.sino_out = sino_out;
   for (const nr::Batch& bt : p.batches) {
     hipStream_t bs = lane_stream(bt);
-    for (const nr::StageLaunch& sl : forward ? bt.fwd : bt.adj) {
+    std::vector<const nr::StageLaunch*> seq;
+    if (fwd)
+      for (const nr::StageLaunch& sl : bt.fwd) seq.push_back(&sl);
+    if (fwd && b) seq.push_back(nullptr);   // the residual of the batch's slices
+    if (adj)
+      for (const nr::StageLaunch& sl : bt.adj) seq.push_back(&sl);
+    for (const nr::StageLaunch* slp : seq) {
+      if (!slp) {
+        hipError_t e = hipSuccess;
+        for (int s : bt.slices) {
+          const nr_slice& sl = p.slices[size_t(s)];
+          const size_t off = size_t(sl.sino_off), cnt = size_t(sl.n_angles) * sl.n_det;
+          e = timed(plan, kStageResidual, bs, [&] { return nrk::launch_residual(sino_out + off, b + off, cnt, bs); });
+          if (e != hipSuccess) return hip_fail(e, where);
+        }
+        continue;
+      }
+      const nr::StageLaunch& sl = *slp;
       const bool spread = sl.stage == nr::Stage::Spread || sl.stage == nr::Stage::SpreadZero;
       hipError_t e = hipSuccess;
       if (spread && p.tune.spread_mode == 1) {
@@ -446,16 +466,25 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_sino) return fail(NR_INVALID_ARG, "d_vol/d_sino is NULL");
   if (nr_status st = pending_error("before radon_fwd")) return st;
-  return run_chain(plan, true, d_vol, nullptr, nullptr, d_sino, static_cast<hipStream_t>(stream),
-                   "radon_fwd launch");
+  return run_batches(plan, true, nullptr, false, d_vol, nullptr, nullptr, d_sino, static_cast<hipStream_t>(stream),
+                     "radon_fwd launch");
 }
 
 nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream) {
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_sino) return fail(NR_INVALID_ARG, "d_vol/d_sino is NULL");
   if (nr_status st = pending_error("before radon_adj")) return st;
-  return run_chain(plan, false, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
-                   "radon_adj launch");
+  return run_batches(plan, false, nullptr, true, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
+                     "radon_adj launch");
+}
+
+nr_status radon_normal(nr_plan* plan, const float* d_vol, const float* d_b, float* d_sino, float* d_vol_out,
+                       nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!d_vol || !d_sino || !d_vol_out) return fail(NR_INVALID_ARG, "radon_normal: NULL argument");
+  if (nr_status st = pending_error("before radon_normal")) return st;
+  return run_batches(plan, true, d_b, true, d_vol, d_vol_out, d_sino, d_sino, static_cast<hipStream_t>(stream),
+                     "radon_normal launch");
 }
 
 nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, float* d_r, double* d_value,
@@ -501,12 +530,10 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
     if (sl.n != n || sl.vol_off != int64_t(z) * n * n)
       return fail(NR_INVALID_ARG, "mbir_step: slices must share N and sit at vol_off = z*N*N");
   }
-  const size_t sino_total = sino_extent(p);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (nr_status s = radon_fwd(plan, d_y, d_scratch, stream)) return s;
-  hipError_t e = timed(plan, kStageResidual, st, [&] { return nrk::launch_residual(d_scratch, d_b, sino_total, st); });
-  if (e != hipSuccess) return hip_fail(e, "mbir_step residual");
-  if (nr_status s = radon_adj(plan, d_scratch, d_grad, stream)) return s;
+  // R^T (R y - b) into d_grad, batch by batch
+  if (nr_status s = radon_normal(plan, d_y, d_b, d_scratch, d_grad, stream)) return s;
+  hipError_t e = hipSuccess;
   if (prior->lambda > 0.0f) {
     const nrk::PriorArgs pa = prior_args(prior);
     e = timed(plan, kStagePrior, st, [&] { return nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, pa, 1.0f, st); });
@@ -540,6 +567,7 @@ nr_status nr_graph_capture_radon(nr_plan* plan, int32_t what, const float* d_vol
   if (!d_sino || ((what & 1) && !d_vol_in) || ((what & 2) && !d_vol_out))
     return fail(NR_INVALID_ARG, "nr_graph_capture_radon: NULL buffer");
   return capture(plan, out, [&](nr_stream s) -> nr_status {
+    if (what == 3) return radon_normal(plan, d_vol_in, nullptr, d_sino, d_vol_out, s);
     if (what & 1)
       if (nr_status st = radon_fwd(plan, d_vol_in, d_sino, s)) return st;
     if (what & 2)

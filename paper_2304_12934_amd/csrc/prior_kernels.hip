@@ -13,6 +13,8 @@
 // accumulates into the gradient in place (Sec. 4, gradients updated in place).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "prior_kernels.hpp"
 
 namespace nrk {
@@ -287,7 +289,8 @@ hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int
 }
 
 hipError_t launch_residual(float* s, const float* b, size_t count, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3(2048), dim3(256), 0, st, s, b, count);
+  const size_t blocks = std::min<size_t>(2048, std::max<size_t>(1, (count + 255) / 256));
+  hipLaunchKernelGGL(k_residual, dim3(unsigned(blocks)), dim3(256), 0, st, s, b, count);
   return hipGetLastError();
 }
 

@@ -174,6 +174,29 @@ class Plan:
             check(lib().radon_adj(self._h, _ptr(sino), _ptr(out), _stream(self.device)), "radon_adj")
         return out
 
+    def normal(self, vol: torch.Tensor, b: torch.Tensor | None = None, sino: torch.Tensor | None = None,
+               out: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+        """``sino = R vol - b`` (``R vol`` without b) and ``out = R^T sino`` in one call.
+
+        Each batch of slices runs its forward, residual and adjoint back to
+        back on one of the plan's streams (no join between the two chains).
+        """
+        _require(vol, self.vol_numel, self.device, "vol")
+        if b is not None:
+            _require(b, self.sino_numel, self.device, "b")
+        if sino is None:
+            sino = torch.empty(self.sino_shape(), dtype=torch.float32, device=self.device)
+        if out is None:
+            out = torch.empty(self.vol_shape(), dtype=torch.float32, device=self.device)
+        _require(sino, self.sino_numel, self.device, "sino")
+        _require(out, self.vol_numel, self.device, "out")
+        if out.data_ptr() == vol.data_ptr():
+            raise ValueError("out must not alias vol")
+        with torch.cuda.device(self.device):
+            check(lib().radon_normal(self._h, _ptr(vol), _ptr(b) if b is not None else None, _ptr(sino), _ptr(out),
+                                     _stream(self.device)), "radon_normal")
+        return sino, out
+
     STAGES = ("fwd_rows", "fwd_cols", "fwd_interp", "adj_radial", "spread", "adj_cols", "adj_rows",
               "residual", "prior", "mbir_update")
 

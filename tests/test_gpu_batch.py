@@ -211,3 +211,27 @@ def test_concurrent_streams_match_one_stream_and_graph(dev):
         torch.cuda.synchronize()
         assert torch.equal(sino, s_ref), k
         assert rel(back.cpu().numpy(), g_ref.cpu().numpy()) < 1e-6, k
+
+
+@pytest.mark.parametrize("streams", [1, 3])
+def test_normal_equals_forward_residual_adjoint(dev, streams):
+    """radon_normal = forward, minus b, then the adjoint, batch by batch on the plan's streams."""
+    from paper_2304_12934_amd import Plan
+    say(f"case: radon_normal vs fwd / residual / adj, {streams} streams")
+    geoms = uneven_geoms(71, 7)
+    rng = np.random.default_rng(72)
+    plan = Plan(geoms, device=dev, tuning={"batch": 2, "streams": streams})
+    x = torch.as_tensor(rng.standard_normal(plan.vol_numel), dtype=torch.float32, device=dev)
+    b = torch.as_tensor(rng.standard_normal(plan.sino_numel), dtype=torch.float32, device=dev)
+    s_ref = plan.fwd(x)
+    r_ref = s_ref - b
+    g_ref = plan.adj(r_ref)
+    g0_ref = plan.adj(s_ref)
+    r, g = plan.normal(x, b)
+    assert torch.equal(r, r_ref)
+    assert rel(g.cpu().numpy(), g_ref.cpu().numpy()) < 1e-6
+    s, g0 = plan.normal(x)
+    assert torch.equal(s, s_ref)
+    assert rel(g0.cpu().numpy(), g0_ref.cpu().numpy()) < 1e-6
+    with pytest.raises(ValueError):
+        plan.normal(x, None, s, x)
