@@ -126,7 +126,7 @@ nr_status nr_plan_destroy(nr_plan* plan);
  *                       one 2560^2 slice, whose grids then stay in the 256 MB
  *                       last-level cache between stages; a slice larger than
  *                       the budget runs alone)
- *   "streams"           1..8 (4 default): batches run round-robin on this many
+ *   "streams"           1..8 (3 default): batches run round-robin on this many
  *                       streams the plan owns (forked from and joined back to
  *                       the caller's stream on every call), each with its own
  *                       scratch, so that the stages of different batches
@@ -138,8 +138,9 @@ nr_status nr_plan_destroy(nr_plan* plan);
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
 
 /* Stage timing for measurement.  While enabled, every stage launch of
- * radon_fwd / radon_adj / radon_normal / mbir_step is bracketed by two HIP
- * events on the stream it runs on (the caller's or one of the plan's).  nr_plan_profile_read waits for the last recorded event
+ * radon_fwd / radon_adj / radon_normal / mbir_step runs on the caller's
+ * stream, one at a time (the plan's own streams are not used), bracketed by
+ * two HIP events.  nr_plan_profile_read waits for the last recorded event
  * and returns, per stage, the summed milliseconds and the launch count, then
  * forgets the records.  Stages: 0 forward rows, 1 forward columns, 2
  * interpolation + radial transform, 3 adjoint radial transform, 4 spreading,

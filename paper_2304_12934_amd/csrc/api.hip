@@ -36,10 +36,13 @@ struct nr_plan {
   int lane_device = -1;
   std::vector<hipStream_t> lanes;
   std::vector<hipEvent_t> lane_done;
+  std::vector<hipEvent_t> lane_skew;
   hipEvent_t fork = nullptr;
   void drop_lanes() {
     for (hipStream_t l : lanes) (void)hipStreamDestroy(l);
     for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+    for (hipEvent_t e : lane_skew) (void)hipEventDestroy(e);
+    lane_skew.clear();
     if (fork) (void)hipEventDestroy(fork);
     lanes.clear();
     lane_done.clear();
@@ -157,6 +160,8 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
     plan->lanes.push_back(l);
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
     plan->lane_done.push_back(ev);
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    plan->lane_skew.push_back(ev);
   }
   return hipSuccess;
 }
@@ -170,7 +175,9 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
 nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const float* vol_in, float* vol_out,
                       const float* sino_in, float* sino_out, hipStream_t st, const char* where) {
   const nr::Plan& p = plan->p;
-  const int nl = p.n_lanes;
+  // while stages are being timed they run one at a time on st, so that each
+  // event pair times its stage alone
+  const int nl = plan->profiling ? 1 : p.n_lanes;
   if (nl > 1) {
     hipError_t e = ensure_lanes(plan, nl);
     if (e == hipSuccess) e = hipEventRecord(plan->fork, st);
@@ -188,7 +195,8 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
   a.vol_out = vol_out;
   a.sino_in = sino_in;
   a.sino_out = sino_out;
-  for (const nr::Batch& bt : p.batches) {
+  for (size_t bi = 0; bi < p.batches.size(); ++bi) {
+    const nr::Batch& bt = p.batches[bi];
     hipStream_t bs = lane_stream(bt);
     std::vector<const nr::StageLaunch*> seq;
     if (fwd)
@@ -196,7 +204,21 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
     if (fwd && b) seq.push_back(nullptr);   // the residual of the batch's slices
     if (adj)
       for (const nr::StageLaunch& sl : bt.adj) seq.push_back(&sl);
-    for (const nr::StageLaunch* slp : seq) {
+    // Lanes start skewed: lane l's first batch waits until lane l-1's first
+    // batch has issued 1/nl of its stages, so concurrent lanes run different
+    // kinds of stage (transforms, gathers, scatters) rather than the same one.
+    const bool first = int(bi) < nl;
+    const size_t skew_at = nl > 1 ? std::max<size_t>(1, seq.size() / size_t(nl)) : 0;
+    if (nl > 1 && first && bt.lane > 0) {
+      const hipError_t e = hipStreamWaitEvent(bs, plan->lane_skew[size_t(bt.lane - 1)], 0);
+      if (e != hipSuccess) return hip_fail(e, where);
+    }
+    for (size_t si = 0; si < seq.size(); ++si) {
+      if (nl > 1 && first && si == skew_at && bt.lane + 1 < nl) {
+        const hipError_t e = hipEventRecord(plan->lane_skew[size_t(bt.lane)], bs);
+        if (e != hipSuccess) return hip_fail(e, where);
+      }
+      const nr::StageLaunch* slp = seq[si];
       if (!slp) {
         hipError_t e = hipSuccess;
         for (int s : bt.slices) {
