@@ -144,7 +144,8 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
  * and returns, per stage, the summed milliseconds and the launch count, then
  * forgets the records.  Stages: 0 forward rows, 1 forward columns, 2
  * interpolation + radial transform, 3 adjoint radial transform, 4 spreading,
- * 5 adjoint columns, 6 adjoint rows, 7 residual, 8 prior, 9 MBIR update. */
+ * 5 adjoint columns, 6 adjoint rows, 7 residual, 8 prior, 9 MBIR update,
+ * 10 clearing the grid tiles that several spreading items share. */
 nr_status nr_plan_profile(nr_plan* plan, int32_t enable);
 nr_status nr_plan_profile_read(nr_plan* plan, double* ms, int64_t* launches, int32_t n_stages);
 

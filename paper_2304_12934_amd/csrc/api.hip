@@ -17,7 +17,7 @@
 // on the caller's stream, read back (and synchronised) on request.
 enum {
   kStageFwdRows = 0, kStageFwdCols, kStageFwdInterp, kStageAdjRadial, kStageSpread, kStageAdjCols,
-  kStageAdjRows, kStageResidual, kStagePrior, kStageUpdate, kStageCount
+  kStageAdjRows, kStageResidual, kStagePrior, kStageUpdate, kStageSpreadClear, kStageCount
 };
 
 struct StageEvents {
@@ -137,7 +137,7 @@ int stage_event_id(nr::Stage s) {
     case nr::Stage::FwdInterp:
     case nr::Stage::FwdRadial: return kStageFwdInterp;
     case nr::Stage::AdjRadial: return kStageAdjRadial;
-    case nr::Stage::SpreadZero:
+    case nr::Stage::SpreadZero: return kStageSpreadClear;
     case nr::Stage::Spread: return kStageSpread;
     case nr::Stage::AdjCols: return kStageAdjCols;
     case nr::Stage::AdjRows: return kStageAdjRows;

@@ -198,7 +198,7 @@ class Plan:
         return sino, out
 
     STAGES = ("fwd_rows", "fwd_cols", "fwd_interp", "adj_radial", "spread", "adj_cols", "adj_rows",
-              "residual", "prior", "mbir_update")
+              "residual", "prior", "mbir_update", "spread_clear")
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every stage launch with HIP events on the launch stream."""
