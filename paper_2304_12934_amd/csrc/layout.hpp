@@ -34,7 +34,7 @@ struct SliceDesc {
   const float* tw_Nt;             // [Nt] exp(-2 pi i m/Nt)
   const double* gxy;              // [na][2] grid step per radial index (sign-flipped)
   const int32_t* flip;            // [na] conjugate flag
-  float* T;                       // [G/2+1][N] complex
+  float* T;                       // [G/2+1][N] complex, in tiles of 4 q x 2 rows
   float* ext;                     // [rows][cols] complex
   float* yh;                      // [na][H] complex
   const int32_t* pts;             // spreading point lists (tile-major)

@@ -448,10 +448,11 @@ nr_status layout_plan(Plan& plan, std::string& err) {
   }
 
   const int ns = int(plan.slices.size());
-  // per-slice scratch: T, ext and yh, each 256-byte aligned
+  // per-slice scratch: T (its q rows rounded up to a multiple of 4), ext and
+  // yh, each 256-byte aligned
   auto scratch_bytes = [&](const Geom& g, size_t& t_off, size_t& ext_off, size_t& yh_off) {
     t_off = 0;
-    ext_off = align_up(size_t(g.G / 2 + 1) * g.key.n * sizeof(f2), 256);
+    ext_off = align_up(size_t((g.G / 2 + 4) / 4 * 4) * g.key.n * sizeof(f2), 256);
     yh_off = align_up(ext_off + size_t(g.rows) * g.cols * sizeof(f2), 256);
     return align_up(yh_off + size_t(g.key.n_angles) * g.H * sizeof(f2), 256);
   };
@@ -517,7 +518,8 @@ nr_status layout_plan(Plan& plan, std::string& err) {
       for (int u = 0; u < (g.key.n_angles + 1) / 2; ++u) v.push_back({s, u});
     };
     for (int G : Gs) add(bt.fwd, Stage::FwdRows, G, true, true, row_pairs);
-    for (int G : Gs) add(bt.fwd, Stage::FwdCols, G, true, false, columns);
+    // columns XCD-interleaved: the four columns of a tile of T share its lines
+    for (int G : Gs) add(bt.fwd, Stage::FwdCols, G, true, true, columns);
     // items of heavy tiles (near the origin) first, over every slice of the batch
     auto heaviest_first = [&](Stage st, auto&& items_of) {
       std::vector<WorkItem> logical;
@@ -559,7 +561,7 @@ nr_status layout_plan(Plan& plan, std::string& err) {
            return g.items;
          }))
       bt.adj.push_back(sl);
-    for (int G : Gs) add(bt.adj, Stage::AdjCols, G, true, false, columns);
+    for (int G : Gs) add(bt.adj, Stage::AdjCols, G, true, true, columns);
     for (int G : Gs) add(bt.adj, Stage::AdjRows, G, true, true, row_pairs);
     plan.batches.push_back(std::move(bt));
   }
@@ -630,7 +632,7 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.gxy = reinterpret_cast<const double*>(d_ws + g.off_gxy);
       d.flip = reinterpret_cast<const int32_t*>(d_ws + g.off_flip);
       char* slot = d_ws + plan.off_slot + size_t(bt.lane) * plan.slot_area + bt.slot_off[k];
-      const size_t ext_off = align_up(size_t(g.G / 2 + 1) * g.key.n * sizeof(f2), 256);
+      const size_t ext_off = align_up(size_t((g.G / 2 + 4) / 4 * 4) * g.key.n * sizeof(f2), 256);
       const size_t yh_off = align_up(ext_off + size_t(g.rows) * g.cols * sizeof(f2), 256);
       d.T = reinterpret_cast<float*>(slot);
       d.ext = reinterpret_cast<float*>(slot + ext_off);
