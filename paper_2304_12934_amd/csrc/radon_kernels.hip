@@ -147,6 +147,15 @@ __device__ __forceinline__ DSlice load_desc(const SliceDesc* p) {
   return d;
 }
 
+// round to the nearest integer, halves up: one instruction (v_cvt_rpi_i32_f32
+// computes floor(x + 0.5)) where __float2int_rn takes two; the spreading
+// rounds each of its ~90 fixed-point contributions per point with it
+__device__ __forceinline__ int round_half_up(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 template <int L>
 __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
   return x < 0 ? x + L : (x >= L ? x - L : x);
@@ -638,7 +647,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
       float wx[W], wy[W];
       point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
       const int i = tid / W, l = tid % W;
-      atomicAdd(&acc_re[(g0x + i + rbase) * TS + g0y + l + cbase], __float2int_rn(q * dc * wx[i] * wy[l]));
+      atomicAdd(&acc_re[(g0x + i + rbase) * TS + g0y + l + cbase], round_half_up(q * dc * wx[i] * wy[l]));
     }
     // one point per round; the slot's registers are picked with compile-time
     // indices (no dynamic register indexing) and the taps are unrolled once
@@ -671,8 +680,8 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
           const float vx = wx[i] * u.x, vy = wx[i] * u.y;
 #pragma unroll
           for (int l = 0; l < W; ++l) {
-            atomicAdd(&acc_re[base + i * TS + l], __float2int_rn(vx * wy[l]));
-            atomicAdd(&acc_im[base + i * TS + l], __float2int_rn(vy * wy[l]));
+            atomicAdd(&acc_re[base + i * TS + l], round_half_up(vx * wy[l]));
+            atomicAdd(&acc_im[base + i * TS + l], round_half_up(vy * wy[l]));
           }
         }
       }
