@@ -280,10 +280,6 @@ struct Lds {
   __device__ __forceinline__ float2& operator[](int i) const { return p[i]; }
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
-// b % 8), each with its own L2; grid-stride launches use multiples of 8.
-constexpr int kXcds = 8;
-
 // ---------------------------------------------------------------------------
 // one Stockham pass and the whole transform
 // ---------------------------------------------------------------------------

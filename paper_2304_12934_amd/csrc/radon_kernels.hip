@@ -49,9 +49,6 @@ namespace nrk {
 // helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float2* c2(float* p) { return reinterpret_cast<float2*>(p); }
-__device__ __forceinline__ const float2* c2(const float* p) { return reinterpret_cast<const float2*>(p); }
-
 // Coordinates of a polar point j on angle table entry (gx, gy): u = j*(gx, gy)
 // in grid cells, first tap g0 = ceil(u - W/2) and the W weights
 // phi(u - g0 - i) from the piecewise polynomial in z = u - g0 - (W-1)/2.
@@ -830,20 +827,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
 
 namespace {
 
-// grid of a launch over n work entries: one workgroup per entry, so the
-// hardware dispatcher balances uneven units (a grid capped at the resident
-// capacity, striding statically over the list, measured slower on the
-// spreading and column stages)
-template <class K>
-int grid_for(K kernel, int threads, int n) {
-  (void)kernel;
-  (void)threads;
-  return std::max(1, n);
-}
-
+// One workgroup per work entry, so the hardware dispatcher balances uneven
+// units (grids capped at the resident capacity, striding over the list,
+// measured slower on the spreading and transform stages).
 template <class K, class... Args>
 hipError_t launch(K kernel, int threads, int n, hipStream_t st, Args... args) {
-  hipLaunchKernelGGL(kernel, dim3(grid_for(kernel, threads, n)), dim3(threads), 0, st, args...);
+  hipLaunchKernelGGL(kernel, dim3(std::max(1, n)), dim3(threads), 0, st, args...);
   return hipGetLastError();
 }
 
