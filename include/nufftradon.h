@@ -36,9 +36,14 @@
  *
  * Ownership.  The caller allocates every device buffer, including the
  * workspace; the library never allocates or frees device memory.  A plan
- * owns host tables only.  All device calls are asynchronous on the given
- * stream and return after enqueueing; a plan is used by one stream at a
- * time.
+ * owns host tables and, once it has run with more than one stream (tuning
+ * key "streams"), that many HIP streams of default priority and their
+ * events, created on first use on the current device and released by
+ * nr_plan_destroy.  All device calls are asynchronous on the given stream
+ * and return after enqueueing: work the plan forks onto its own streams
+ * waits for what was enqueued on the given stream before the call, and the
+ * given stream waits for all of it before anything enqueued after the call.
+ * A plan is used by one stream at a time (its scratch is shared).
  *
  * Errors.  Every call returns an nr_status and never aborts.  Arguments are
  * validated before anything is enqueued.  nr_last_error() gives a
