@@ -221,18 +221,25 @@ def add_cracks(vol: torch.Tensor, rng: np.random.Generator, count: int,
                                   torch.ones((), dtype=vol.dtype, device=dev))
     if blur_sigma > 0:
         rad = int(math.ceil(3 * blur_sigma))
-        t = torch.arange(-rad, rad + 1, dtype=torch.float64, device=dev)
-        k = torch.exp(-0.5 * (t / blur_sigma) ** 2)
+        t = np.arange(-rad, rad + 1, dtype=np.float64)
+        k = np.exp(-0.5 * (t / blur_sigma) ** 2)
         k = k / k.sum()
-        m = keep[None, None]
-        m = torch.nn.functional.conv3d(torch.nn.functional.pad(m, (rad, rad, 0, 0, 0, 0), mode="replicate"),
-                                       k.view(1, 1, 1, 1, -1))
-        m = torch.nn.functional.conv3d(torch.nn.functional.pad(m, (0, 0, rad, rad, 0, 0), mode="replicate"),
-                                       k.view(1, 1, 1, -1, 1))
-        m = torch.nn.functional.conv3d(torch.nn.functional.pad(m, (0, 0, 0, 0, rad, rad), mode="replicate"),
-                                       k.view(1, 1, -1, 1, 1))
-        keep = m[0, 0]
+        for dim in range(3):
+            keep = _smooth_axis(keep, k, dim)
     return vol * keep
+
+
+def _smooth_axis(m: torch.Tensor, k: np.ndarray, dim: int) -> torch.Tensor:
+    """Correlate ``m`` with the odd-length taps ``k`` along ``dim``, edges replicated."""
+    rad = (len(k) - 1) // 2
+    size = m.shape[dim]
+    lo = m.narrow(dim, 0, 1).expand(*[rad if d == dim else -1 for d in range(m.dim())])
+    hi = m.narrow(dim, size - 1, 1).expand(*[rad if d == dim else -1 for d in range(m.dim())])
+    padded = torch.cat([lo, m, hi], dim=dim)
+    out = torch.zeros_like(m)
+    for i, w in enumerate(k):
+        out += float(w) * padded.narrow(dim, i, size)
+    return out
 
 
 def gaussian_blob(n: int, centre: tuple[float, float], s: float, amp: float = 1.0) -> np.ndarray:
