@@ -244,6 +244,8 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
     ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-stack leg")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the filtered back-projection and rotation-axis offset timings")
     ap.add_argument("--batched-slices", type=int, default=96)
     ap.add_argument("--mbir-n", type=int, default=1280)
     ap.add_argument("--mbir-slices", type=int, default=64)
@@ -360,6 +362,33 @@ def main() -> int:
     mb = model_bytes_per_slice(n, nd, na)
     step_gbs = mb * S / (ms_per_step * 1e-3) / 1e9
 
+    # the operators beside the metric, on the same stack: the plain adjoint,
+    # filtered back-projection (adjoint with the ramp x Butterworth weight) and
+    # forward + adjoint with the rotation axis 3.25 bins off centre
+    extensions = None
+    if not args.no_extensions:
+        def rate(fn, k):
+            for _ in range(2):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(k):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return round(S * k / (e0.elapsed_time(e1) / 1e3), 2)
+
+        extensions = {"adj_slices_per_s": rate(lambda: plan.adj(sino, back), args.steps),
+                      "fbp_butterworth_slices_per_s": rate(lambda: plan.fbp(sino, back, filter="butterworth"),
+                                                           args.steps)}
+        plan_c = Plan.uniform_stack(n, nd, angles, S, center=3.25, device=dev, tuning=tuning or None)
+        extensions["fwd_adj_axis_offset_slices_per_s"] = rate(lambda: plan_c.normal(vol, None, sino, back),
+                                                               args.steps)
+        del plan_c
+        print(f"[bench] extensions {extensions}", file=sys.stderr, flush=True)
+
     mbir = None
     if not args.no_mbir:
         del vol, sino, back, plan
@@ -411,6 +440,7 @@ def main() -> int:
         "stages": stage_report,
         "mbir": mbir,
         "uneven_stack": batched,
+        "extensions": extensions,
         "wall_s": round(wall, 3),
         "git": sha,
     }

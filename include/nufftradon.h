@@ -26,6 +26,9 @@
  * with k_l = (l - N_t/2)/N_t; radon_adj is its exact transpose for real
  * inner products.  The non-uniform FFT approximates Fhat with a
  * Kaiser-Bessel kernel of width W on a grid oversampled by sigma = 2.
+ * A slice whose rotation axis projects to bin N_t/2 + c (nr_slice.center)
+ * has t_m replaced by t_m - c: the Fourier shift of Sec. 4.1, applied as a
+ * phase exp(-2 pi i k c) on each radial line.
  *
  * Stacks.  A plan describes n_slices slices, each with its own size N,
  * detector count N_t and angle set, addressed by element offsets into flat
@@ -77,11 +80,24 @@ typedef void* nr_stream;
 typedef struct nr_plan nr_plan;
 
 /* One slice of a stack.  n: slice width N (even, >= 8); n_det: detector
- * bins N_t (even, >= 8); n_angles >= 1.  Offsets are element offsets. */
+ * bins N_t (even, >= 8); n_angles >= 1.  Offsets are element offsets.
+ * center: offset c of the rotation axis from the detector centre, in bins
+ * (the axis projects to bin N_t/2 + c); finite, |c| <= N_t/2; 0 for a
+ * centred axis. */
 typedef struct {
   int32_t n, n_det, n_angles;
   int64_t vol_off, sino_off, angle_off;
+  double center;
 } nr_slice;
+
+/* Filter of radon_fbp.  filter: NR_FBP_RAMP (|k|) or NR_FBP_BUTTERWORTH
+ * (|k| / (1 + (|k|/cutoff)^(2 order))); cutoff in cycles per pixel (> 0;
+ * the Nyquist frequency is 0.5), order 1..16 (both ignored for the ramp). */
+enum { NR_FBP_RAMP = 0, NR_FBP_BUTTERWORTH = 1 };
+typedef struct {
+  int32_t filter, order;
+  double cutoff;
+} nr_fbp;
 
 /* Non-uniform FFT parameters.  sigma: oversampling (only 2.0 is built);
  * width: kernel width W in grid cells (6, 7 or 8); beta <= 0 selects the
@@ -163,6 +179,14 @@ nr_status radon_fwd(nr_plan* plan, const float* d_vol, float* d_sino, nr_stream 
  * of radon_fwd).  d_sino: float32 input; d_vol: float32 output,
  * overwritten.  Device pointers. */
 nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream stream);
+
+/* Filtered back-projection for every slice (Sec. 2.1, eq. "inverse_radon"
+ * discretised with dtheta = pi/N_theta and dk = 1/N_t):
+ *     g(x) = (pi/N_theta) Re sum_a (1/N_t) sum_l w(k_l) Yhat_a(k_l) exp(2 pi i k_l <x, n_a>),
+ *     Yhat_a(k) = sum_m y[a][m] exp(-2 pi i k (t_m - c)),
+ * w from *filter.  radon_adj with the radial weight w(k) pi/N_theta applied
+ * on each line; same buffers and layouts as radon_adj. */
+nr_status radon_fbp(nr_plan* plan, const nr_fbp* filter, const float* d_sino, float* d_vol, nr_stream stream);
 
 /* The gradient of the data term (Sec. 3, eq. "gradient"): d_sino = R f - b
  * (R f when d_b is NULL) and d_vol_out = R^T d_sino, for every slice.  Same

@@ -24,7 +24,15 @@ NR_INTERNAL = 6
 
 class NrSlice(ctypes.Structure):
     _fields_ = [("n", c_int32), ("n_det", c_int32), ("n_angles", c_int32),
-                ("vol_off", c_int64), ("sino_off", c_int64), ("angle_off", c_int64)]
+                ("vol_off", c_int64), ("sino_off", c_int64), ("angle_off", c_int64), ("center", c_double)]
+
+
+NR_FBP_RAMP = 0
+NR_FBP_BUTTERWORTH = 1
+
+
+class NrFbp(ctypes.Structure):
+    _fields_ = [("filter", c_int32), ("order", c_int32), ("cutoff", c_double)]
 
 
 class NrNufft(ctypes.Structure):
@@ -61,6 +69,7 @@ SIGNATURES = {
     "nr_plan_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
     "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "radon_fbp": (c_int32, [c_void_p, POINTER(NrFbp), c_void_p, c_void_p, c_void_p]),
     "radon_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_normal": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,

@@ -173,7 +173,8 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
 // st; st then waits for every lane.  Each batch's adjoint follows its own
 // forward on its lane, with no join in between.
 nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const float* vol_in, float* vol_out,
-                      const float* sino_in, float* sino_out, hipStream_t st, const char* where) {
+                      const float* sino_in, float* sino_out, hipStream_t st, const char* where,
+                      const nr_fbp* fbp = nullptr) {
   const nr::Plan& p = plan->p;
   // while stages are being timed they run one at a time on st, so that each
   // event pair times its stage alone
@@ -195,6 +196,9 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
   a.vol_out = vol_out;
   a.sino_in = sino_in;
   a.sino_out = sino_out;
+  a.fbp_filter = fbp ? fbp->filter : -1;
+  a.fbp_order = fbp ? fbp->order : 0;
+  a.fbp_inv_cutoff = fbp && fbp->filter == NR_FBP_BUTTERWORTH ? float(1.0 / fbp->cutoff) : 0.f;
   for (size_t bi = 0; bi < p.batches.size(); ++bi) {
     const nr::Batch& bt = p.batches[bi];
     hipStream_t bs = lane_stream(bt);
@@ -393,6 +397,8 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
     if ((e = up(p.off_deapod.at(kv.first), kv.second.data(), kv.second.size() * sizeof(float)))) break;
   for (auto& kv : p.twiddle)
     if (!e && (e = up(p.off_twiddle.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) break;
+  for (auto& kv : p.shift)
+    if (!e && (e = up(p.off_shift.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) break;
   for (nr::Geom& g : p.geoms) {
     if (e) break;
     if ((e = up(g.off_gxy, g.gxy.data(), g.gxy.size() * sizeof(double)))) break;
@@ -498,6 +504,19 @@ nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream 
   if (nr_status st = pending_error("before radon_adj")) return st;
   return run_batches(plan, false, nullptr, true, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
                      "radon_adj launch");
+}
+
+nr_status radon_fbp(nr_plan* plan, const nr_fbp* filter, const float* d_sino, float* d_vol, nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!filter || !d_vol || !d_sino) return fail(NR_INVALID_ARG, "radon_fbp: NULL argument");
+  if (filter->filter != NR_FBP_RAMP && filter->filter != NR_FBP_BUTTERWORTH)
+    return fail(NR_INVALID_ARG, "radon_fbp: filter must be NR_FBP_RAMP or NR_FBP_BUTTERWORTH");
+  if (filter->filter == NR_FBP_BUTTERWORTH &&
+      (!(filter->cutoff > 0.0 && filter->cutoff < 1e30) || filter->order < 1 || filter->order > 16))
+    return fail(NR_INVALID_ARG, "radon_fbp: Butterworth needs a finite cutoff > 0 and 1 <= order <= 16");
+  if (nr_status st = pending_error("before radon_fbp")) return st;
+  return run_batches(plan, false, nullptr, true, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
+                     "radon_fbp launch", filter);
 }
 
 nr_status radon_normal(nr_plan* plan, const float* d_vol, const float* d_b, float* d_sino, float* d_vol_out,

@@ -32,6 +32,7 @@ struct SliceDesc {
   const float* deapod;            // [N] 1/phihat((i - N/2)/G)
   const float* tw_G;              // [G] exp(-2 pi i m/G)
   const float* tw_Nt;             // [Nt] exp(-2 pi i m/Nt)
+  const float* shift;             // [Nt/2+1] exp(-2 pi i j c/Nt) for a rotation axis at bin Nt/2 + c; null if c = 0
   const double* gxy;              // [na][2] grid step per radial index (sign-flipped)
   const int32_t* flip;            // [na] conjugate flag
   float* T;                       // [G/2+1][N] complex, in tiles of 4 q x 2 rows

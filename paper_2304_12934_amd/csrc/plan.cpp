@@ -325,6 +325,10 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
       err = "slice " + std::to_string(s) + ": negative offset";
       return NR_INVALID_ARG;
     }
+    if (!std::isfinite(sl.center) || std::fabs(sl.center) > 0.5 * sl.n_det) {
+      err = "slice " + std::to_string(s) + ": center must be finite with |center| <= n_det/2";
+      return NR_INVALID_ARG;
+    }
     const int G = int(sigma * sl.n);
     if (!fft_length_supported(G) || !fft_length_supported(sl.n_det)) {
       err = "slice " + std::to_string(s) + ": FFT length " + std::to_string(G) + " or " +
@@ -394,6 +398,20 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
       }
       plan.twiddle[L] = tw;
     }
+  }
+  // rotation-axis phases exp(-2 pi i k_j c) on the half-line k_j = j/N_t,
+  // one table per distinct (N_t, c) with c != 0
+  for (const nr_slice& sl : plan.slices) {
+    const std::pair<int, double> key{sl.n_det, sl.center};
+    if (sl.center == 0.0 || plan.shift.count(key)) continue;
+    const int H = sl.n_det / 2 + 1;
+    std::vector<f2> ph(H);
+    for (int j = 0; j < H; ++j) {
+      // reduce j*c/N_t modulo 1 in float64 before the trigonometry
+      double turns = std::fmod(double(j) * sl.center, double(sl.n_det)) / double(sl.n_det);
+      ph[j] = {float(std::cos(2.0 * M_PI * turns)), float(-std::sin(2.0 * M_PI * turns))};
+    }
+    plan.shift[key] = ph;
   }
 
   return NR_OK;
@@ -576,6 +594,10 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     plan.off_twiddle[kv.first] = off;
     off = align_up(off + kv.second.size() * sizeof(f2), 256);
   }
+  for (auto& kv : plan.shift) {
+    plan.off_shift[kv.first] = off;
+    off = align_up(off + kv.second.size() * sizeof(f2), 256);
+  }
   for (Geom& g : plan.geoms) {
     g.off_gxy = off;
     off = align_up(off + g.gxy.size() * sizeof(double), 256);
@@ -629,6 +651,9 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.deapod = reinterpret_cast<const float*>(d_ws + plan.off_deapod.at(sl.n));
       d.tw_G = reinterpret_cast<const float*>(d_ws + plan.off_twiddle.at(g.G));
       d.tw_Nt = reinterpret_cast<const float*>(d_ws + plan.off_twiddle.at(sl.n_det));
+      d.shift = sl.center == 0.0
+                    ? nullptr
+                    : reinterpret_cast<const float*>(d_ws + plan.off_shift.at({sl.n_det, sl.center}));
       d.gxy = reinterpret_cast<const double*>(d_ws + g.off_gxy);
       d.flip = reinterpret_cast<const int32_t*>(d_ws + g.off_flip);
       char* slot = d_ws + plan.off_slot + size_t(bt.lane) * plan.slot_area + bt.slot_off[k];

@@ -127,6 +127,8 @@ struct Plan {
   std::map<int, size_t> off_deapod;
   std::map<int, std::vector<f2>> twiddle;     // L -> exp(-2 pi i m / L)
   std::map<int, size_t> off_twiddle;
+  std::map<std::pair<int, double>, std::vector<f2>> shift;   // (N_t, c) -> exp(-2 pi i j c / N_t), j <= N_t/2
+  std::map<std::pair<int, double>, size_t> off_shift;
 
   Tuning tune;
   bool laid_out = false;

@@ -106,6 +106,7 @@ struct DSlice {
   const NR_G float* deapod;
   const NR_G float2* tw_G;
   const NR_G float2* tw_Nt;
+  const NR_G float2* shift;
   const NR_G double* gxy;
   const NR_G int32_t* flip;
   NR_G float2* T;
@@ -129,6 +130,7 @@ __device__ __forceinline__ DSlice load_desc(const SliceDesc* p) {
   d.deapod = (const NR_G float*)s.deapod;
   d.tw_G = (const NR_G float2*)s.tw_G;
   d.tw_Nt = (const NR_G float2*)s.tw_Nt;
+  d.shift = (const NR_G float2*)s.shift;
   d.gxy = (const NR_G double*)s.gxy;
   d.flip = (const NR_G int32_t*)s.flip;
   d.T = (NR_G float2*)s.T;
@@ -481,6 +483,11 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
     NR_STRIDED(j, H, T) {
       float2 X = x0[j], Y = x1[j];
       if (!has1) Y = make_float2(0.f, 0.f);
+      if (d.shift) {   // rotation axis at bin L/2 + c: evaluate the line at t - c
+        const float2 p = d.shift[j];
+        X = c_mul(X, p);
+        Y = c_mul(Y, p);
+      }
       if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
         X.y = 0.f;
         Y.y = 0.f;
@@ -503,6 +510,21 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 // A1: radial transform of two sinogram rows
 // ---------------------------------------------------------------------------
+
+// Filtered back-projection weight of half-line index j of an L-point line:
+// (pi/n_angles) |k| B(k) with k = j/L cycles per pixel and B = 1 (ramp) or
+// 1/(1 + (k/cutoff)^(2 order)) (Butterworth).
+__device__ __forceinline__ float fbp_weight(const LaunchArgs& a, int j, int L, int n_angles) {
+  const float k = float(j) / float(L);
+  float w = k;
+  if (a.fbp_filter == 1) {
+    const float x = k * a.fbp_inv_cutoff, x2 = x * x;
+    float pw = 1.f;
+    for (int i = 0; i < a.fbp_order; ++i) pw *= x2;
+    w = k / (1.f + pw);
+  }
+  return w * (3.14159265358979f / float(n_angles));
+}
 
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(LaunchArgs a) {
@@ -527,9 +549,17 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(LaunchArgs a) {
     const float inv = 1.0f / float(L);
     NR_STRIDED(j, H, T) {
       const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
-      const float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
-      o0[j] = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
-      if (has1) o0[H + j] = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+      float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
+      if (a.fbp_filter >= 0) w *= fbp_weight(a, j, L, d.na);
+      float2 A = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
+      float2 B = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+      if (d.shift) {   // transpose of the forward's phase
+        const float2 q = c_conj(d.shift[j]);
+        A = c_mul(A, q);
+        B = c_mul(B, q);
+      }
+      o0[j] = A;
+      if (has1) o0[H + j] = B;
     }
     __syncthreads();
   }

@@ -17,6 +17,9 @@ struct LaunchArgs {
   float* vol_out;
   const float* sino_in;
   float* sino_out;
+  int fbp_filter;           // adjoint radial weight: -1 none, 0 ramp, 1 ramp x Butterworth
+  int fbp_order;
+  float fbp_inv_cutoff;
 };
 
 // Kaiser-Bessel tap polynomials: c[i*(W+3) + k] is the z^k coefficient of tap i.

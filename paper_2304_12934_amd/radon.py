@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NrMbir, NrNufft, NrPrior, NrSlice, check, lib
+from ._lib import NR_FBP_BUTTERWORTH, NR_FBP_RAMP, NrFbp, NrMbir, NrNufft, NrPrior, NrSlice, check, lib
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:
@@ -42,10 +42,13 @@ def _require(t: torch.Tensor, numel: int, device: torch.device, name: str) -> No
 
 @dataclass
 class SliceGeometry:
-    """One slice of a stack: width ``n``, detector bins ``n_det``, angles (radians)."""
+    """One slice of a stack: width ``n``, detector bins ``n_det``, angles (radians)
+    and ``center``, the offset in bins of the rotation axis from the detector
+    centre (the axis projects to bin ``n_det/2 + center``)."""
     n: int
     n_det: int
     angles: np.ndarray
+    center: float = 0.0
 
 
 class Plan:
@@ -79,7 +82,7 @@ class Plan:
                 angle_index[key] = a_off
                 angle_chunks.append(ang)
                 angle_off += len(ang)
-            slices[i] = NrSlice(int(g.n), int(g.n_det), len(ang), vol_off, sino_off, a_off)
+            slices[i] = NrSlice(int(g.n), int(g.n_det), len(ang), vol_off, sino_off, a_off, float(g.center))
             self.vol_offsets.append(vol_off)
             self.sino_offsets.append(sino_off)
             vol_off += int(g.n) * int(g.n)
@@ -136,9 +139,9 @@ class Plan:
         return Graph(h, self, (vol_in, sino, vol_out))
 
     @classmethod
-    def uniform_stack(cls, n: int, n_det: int, angles, n_slices: int = 1, **kw) -> "Plan":
+    def uniform_stack(cls, n: int, n_det: int, angles, n_slices: int = 1, center: float = 0.0, **kw) -> "Plan":
         ang = np.asarray(angles, dtype=np.float64)
-        return cls([SliceGeometry(n, n_det, ang) for _ in range(n_slices)], **kw)
+        return cls([SliceGeometry(n, n_det, ang, center) for _ in range(n_slices)], **kw)
 
     # --------------------------------------------------------------- shapes
     @property
@@ -172,6 +175,24 @@ class Plan:
         _require(out, self.vol_numel, self.device, "out")
         with torch.cuda.device(self.device):
             check(lib().radon_adj(self._h, _ptr(sino), _ptr(out), _stream(self.device)), "radon_adj")
+        return out
+
+    def fbp(self, sino: torch.Tensor, out: torch.Tensor | None = None, filter: str = "ramp", order: int = 2,
+            cutoff: float = 0.25) -> torch.Tensor:
+        """Filtered back-projections of every slice (float32): ``filter`` is
+        ``"ramp"`` (|k|) or ``"butterworth"`` (|k| / (1 + (|k|/cutoff)^(2 order)),
+        cutoff in cycles per pixel)."""
+        codes = {"ramp": NR_FBP_RAMP, "butterworth": NR_FBP_BUTTERWORTH}
+        if filter not in codes:
+            raise ValueError(f"filter must be one of {sorted(codes)}")
+        _require(sino, self.sino_numel, self.device, "sino")
+        if out is None:
+            out = torch.empty(self.vol_shape(), dtype=torch.float32, device=self.device)
+        _require(out, self.vol_numel, self.device, "out")
+        params = NrFbp(codes[filter], int(order), float(cutoff))
+        with torch.cuda.device(self.device):
+            check(lib().radon_fbp(self._h, ctypes.byref(params), _ptr(sino), _ptr(out), _stream(self.device)),
+                  "radon_fbp")
         return out
 
     def normal(self, vol: torch.Tensor, b: torch.Tensor | None = None, sino: torch.Tensor | None = None,

@@ -91,11 +91,19 @@ def test_plan_validation_status_codes(L):
     bad[3] = np.nan
     assert _create(L, [(128, 128, 10, 0, 0, 0)], bad)[0] == _lib.NR_INVALID_ARG
     assert L.nr_last_error()
+    # rotation-axis offset: finite and within half the detector
+    assert _create(L, [(128, 128, 10, 0, 0, 0, float("nan"))], ang)[0] == _lib.NR_INVALID_ARG
+    assert _create(L, [(128, 128, 10, 0, 0, 0, 64.5)], ang)[0] == _lib.NR_INVALID_ARG
+    st, h = _create(L, [(128, 128, 10, 0, 0, 0, -64.0)], ang)
+    assert st == _lib.NR_OK
+    L.nr_plan_destroy(h)
     st, h = _create(L, [(128, 128, 10, 0, 0, 0)], ang)
     assert st == _lib.NR_OK
     # binding a NULL workspace is refused before any device work
     assert L.nr_plan_bind(h, None, 0, None) == _lib.NR_INVALID_ARG
     assert L.radon_fwd(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == _lib.NR_INVALID_ARG  # not bound
+    ramp = _lib.NrFbp(_lib.NR_FBP_RAMP, 0, 0.0)
+    assert L.radon_fbp(h, ctypes.byref(ramp), ctypes.c_void_p(8), ctypes.c_void_p(8), None) == _lib.NR_INVALID_ARG
     L.nr_plan_destroy(h)
 
 
