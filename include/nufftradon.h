@@ -188,6 +188,29 @@ nr_status radon_adj(nr_plan* plan, const float* d_sino, float* d_vol, nr_stream 
  * on each line; same buffers and layouts as radon_adj. */
 nr_status radon_fbp(nr_plan* plan, const nr_fbp* filter, const float* d_sino, float* d_vol, nr_stream stream);
 
+/* Host-resident stacks streamed through the GPU (Sec. 4.1: the partition
+ * along the rotation axis, sub-partitions copied asynchronously).  The plan
+ * describes one chunk; h_in and h_out hold n_chunks chunks back to back in
+ * host memory, each laid out as the plan's flat buffers (a chunk's volume
+ * has the extent of the plan's volume layout, its sinogram that of the
+ * sinogram layout).  what: NR_STREAM_FWD (volume -> sinogram), NR_STREAM_ADJ
+ * (sinogram -> volume) or NR_STREAM_FBP (sinogram -> volume, with *filter;
+ * filter is ignored otherwise and may be NULL).
+ * d_in[0..1] and d_out[0..1]: two caller-owned device buffers of one chunk
+ * each, in the input and output layouts of `what`; chunk i uses d_in[i%2]
+ * and d_out[i%2], so the copy of chunk i+1 to the device and of chunk i-1
+ * back to the host overlap the computation of chunk i.  The copies run on
+ * two streams the plan owns (default priority), the computation on
+ * `stream`, which on return waits for the last copy back; h_out is complete
+ * once `stream` has drained.  Host memory should be pinned (hipHostMalloc)
+ * for the copies to be asynchronous; pageable memory gives the same result
+ * with the copies serialised.  n_chunks = 0 enqueues nothing.  The four
+ * device buffers must be distinct; results equal those of the
+ * device-resident calls chunk by chunk. */
+enum { NR_STREAM_FWD = 1, NR_STREAM_ADJ = 2, NR_STREAM_FBP = 3 };
+nr_status radon_stream(nr_plan* plan, int32_t what, const nr_fbp* filter, const float* h_in, float* h_out,
+                       int64_t n_chunks, float* const* d_in, float* const* d_out, nr_stream stream);
+
 /* The gradient of the data term (Sec. 3, eq. "gradient"): d_sino = R f - b
  * (R f when d_b is NULL) and d_vol_out = R^T d_sino, for every slice.  Same
  * values as radon_fwd, the subtraction and radon_adj in sequence; each batch

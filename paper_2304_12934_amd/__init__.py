@@ -16,7 +16,8 @@ from .radon import (  # noqa: F401
     kb_eval,
     power_lipschitz,
     qggmrf_grad,
+    stream_stack,
 )
 
 __all__ = ["Plan", "Graph", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
-           "power_lipschitz", "kb_eval"]
+           "power_lipschitz", "kb_eval", "stream_stack"]

@@ -29,6 +29,9 @@ class NrSlice(ctypes.Structure):
 
 NR_FBP_RAMP = 0
 NR_FBP_BUTTERWORTH = 1
+NR_STREAM_FWD = 1
+NR_STREAM_ADJ = 2
+NR_STREAM_FBP = 3
 
 
 class NrFbp(ctypes.Structure):
@@ -70,6 +73,8 @@ SIGNATURES = {
     "radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_fbp": (c_int32, [c_void_p, POINTER(NrFbp), c_void_p, c_void_p, c_void_p]),
+    "radon_stream": (c_int32, [c_void_p, c_int32, POINTER(NrFbp), c_void_p, c_void_p, c_int64,
+                               POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     "radon_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "radon_normal": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qggmrf_grad": (c_int32, [c_void_p, c_int32, c_int32, POINTER(NrPrior), c_float, c_void_p, c_void_p,

@@ -38,6 +38,20 @@ struct nr_plan {
   std::vector<hipEvent_t> lane_done;
   std::vector<hipEvent_t> lane_skew;
   hipEvent_t fork = nullptr;
+  // host streaming: copy-in and copy-out streams and the events that order
+  // the two chunk buffers between them and the compute stream
+  int io_device = -1;
+  hipStream_t io_in = nullptr, io_out = nullptr;
+  hipEvent_t io_fork = nullptr, io_done = nullptr;
+  hipEvent_t h2d_done[2] = {nullptr, nullptr}, comp_done[2] = {nullptr, nullptr}, d2h_done[2] = {nullptr, nullptr};
+  void drop_io() {
+    for (hipStream_t* st : {&io_in, &io_out})
+      if (*st) (void)hipStreamDestroy(*st), *st = nullptr;
+    for (hipEvent_t* e : {&io_fork, &io_done, &h2d_done[0], &h2d_done[1], &comp_done[0], &comp_done[1],
+                          &d2h_done[0], &d2h_done[1]})
+      if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+    io_device = -1;
+  }
   void drop_lanes() {
     for (hipStream_t l : lanes) (void)hipStreamDestroy(l);
     for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
@@ -56,6 +70,7 @@ struct nr_plan {
     }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     drop_lanes();
+    drop_io();
   }
 };
 
@@ -267,6 +282,27 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
     if (e != hipSuccess) return hip_fail(e, where);
   }
   return NR_OK;
+}
+
+hipError_t ensure_io(nr_plan* plan) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (plan->io_device == dev && plan->io_in) return hipSuccess;
+  plan->drop_io();
+  plan->io_device = dev;
+  for (hipStream_t* st : {&plan->io_in, &plan->io_out})
+    if ((e = hipStreamCreateWithFlags(st, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (hipEvent_t* ev : {&plan->io_fork, &plan->io_done, &plan->h2d_done[0], &plan->h2d_done[1],
+                         &plan->comp_done[0], &plan->comp_done[1], &plan->d2h_done[0], &plan->d2h_done[1]})
+    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+size_t vol_extent(const nr::Plan& p) {
+  size_t n = 0;
+  for (const nr_slice& sl : p.slices) n = std::max(n, size_t(sl.vol_off) + size_t(sl.n) * sl.n);
+  return n;
 }
 
 size_t sino_extent(const nr::Plan& p) {
@@ -517,6 +553,71 @@ nr_status radon_fbp(nr_plan* plan, const nr_fbp* filter, const float* d_sino, fl
   if (nr_status st = pending_error("before radon_fbp")) return st;
   return run_batches(plan, false, nullptr, true, nullptr, d_vol, d_sino, nullptr, static_cast<hipStream_t>(stream),
                      "radon_fbp launch", filter);
+}
+
+nr_status radon_stream(nr_plan* plan, int32_t what, const nr_fbp* filter, const float* h_in, float* h_out,
+                       int64_t n_chunks, float* const* d_in, float* const* d_out, nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (what != NR_STREAM_FWD && what != NR_STREAM_ADJ && what != NR_STREAM_FBP)
+    return fail(NR_INVALID_ARG, "radon_stream: what must be NR_STREAM_FWD, NR_STREAM_ADJ or NR_STREAM_FBP");
+  if (n_chunks < 0) return fail(NR_INVALID_ARG, "radon_stream: n_chunks < 0");
+  if (n_chunks == 0) return NR_OK;
+  if (!h_in || !h_out || !d_in || !d_out || !d_in[0] || !d_in[1] || !d_out[0] || !d_out[1])
+    return fail(NR_INVALID_ARG, "radon_stream: NULL argument");
+  const float* bufs[4] = {d_in[0], d_in[1], d_out[0], d_out[1]};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (bufs[i] == bufs[j]) return fail(NR_INVALID_ARG, "radon_stream: the four device buffers must be distinct");
+  if (what == NR_STREAM_FBP) {
+    if (!filter) return fail(NR_INVALID_ARG, "radon_stream: NR_STREAM_FBP needs a filter");
+    if (filter->filter != NR_FBP_RAMP && filter->filter != NR_FBP_BUTTERWORTH)
+      return fail(NR_INVALID_ARG, "radon_stream: filter must be NR_FBP_RAMP or NR_FBP_BUTTERWORTH");
+    if (filter->filter == NR_FBP_BUTTERWORTH &&
+        (!(filter->cutoff > 0.0 && filter->cutoff < 1e30) || filter->order < 1 || filter->order > 16))
+      return fail(NR_INVALID_ARG, "radon_stream: Butterworth needs a finite cutoff > 0 and 1 <= order <= 16");
+  }
+  if (nr_status st = pending_error("before radon_stream")) return st;
+  const nr::Plan& p = plan->p;
+  const bool fwd = what == NR_STREAM_FWD;
+  const size_t n_in = fwd ? vol_extent(p) : sino_extent(p), n_out = fwd ? sino_extent(p) : vol_extent(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = ensure_io(plan);
+  // the copy streams start after the work already on the caller's stream
+  if (e == hipSuccess) e = hipEventRecord(plan->io_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_in, plan->io_fork, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_out, plan->io_fork, 0);
+  if (e != hipSuccess) return hip_fail(e, "radon_stream set-up");
+  for (int64_t i = 0; i < n_chunks; ++i) {
+    const int b = int(i & 1);
+    // copy in: buffer b is free once the computation of chunk i-2 is done
+    if (i >= 2) e = hipStreamWaitEvent(plan->io_in, plan->comp_done[b], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_in[b], h_in + size_t(i) * n_in, n_in * sizeof(float), hipMemcpyHostToDevice,
+                         plan->io_in);
+    if (e == hipSuccess) e = hipEventRecord(plan->h2d_done[b], plan->io_in);
+    // compute: after its input arrived and chunk i-2's output left d_out[b]
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->h2d_done[b], 0);
+    if (e == hipSuccess && i >= 2) e = hipStreamWaitEvent(st, plan->d2h_done[b], 0);
+    if (e != hipSuccess) return hip_fail(e, "radon_stream copy in");
+    nr_status s = fwd ? run_batches(plan, true, nullptr, false, d_in[b], nullptr, nullptr, d_out[b], st,
+                                    "radon_stream launch")
+                      : run_batches(plan, false, nullptr, true, nullptr, d_out[b], d_in[b], nullptr, st,
+                                    "radon_stream launch", what == NR_STREAM_FBP ? filter : nullptr);
+    if (s != NR_OK) return s;
+    e = hipEventRecord(plan->comp_done[b], st);
+    // copy out
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_out, plan->comp_done[b], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_out + size_t(i) * n_out, d_out[b], n_out * sizeof(float), hipMemcpyDeviceToHost,
+                         plan->io_out);
+    if (e == hipSuccess) e = hipEventRecord(plan->d2h_done[b], plan->io_out);
+    if (e != hipSuccess) return hip_fail(e, "radon_stream copy out");
+  }
+  // the caller's stream waits for the last copy back (and so for every copy)
+  e = hipEventRecord(plan->io_done, plan->io_out);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->io_done, 0);
+  if (e != hipSuccess) return hip_fail(e, "radon_stream join");
+  return NR_OK;
 }
 
 nr_status radon_normal(nr_plan* plan, const float* d_vol, const float* d_b, float* d_sino, float* d_vol_out,

@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NR_FBP_BUTTERWORTH, NR_FBP_RAMP, NrFbp, NrMbir, NrNufft, NrPrior, NrSlice, check, lib
+from ._lib import (NR_FBP_BUTTERWORTH, NR_FBP_RAMP, NR_STREAM_ADJ, NR_STREAM_FBP, NR_STREAM_FWD, NrFbp, NrMbir,
+                   NrNufft, NrPrior, NrSlice, check, lib)
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:
@@ -194,6 +195,48 @@ class Plan:
             check(lib().radon_fbp(self._h, ctypes.byref(params), _ptr(sino), _ptr(out), _stream(self.device)),
                   "radon_fbp")
         return out
+
+    def stream(self, what: str, host_in: torch.Tensor, host_out: torch.Tensor | None = None,
+               filter: str = "ramp", order: int = 2, cutoff: float = 0.25, sync: bool = True) -> torch.Tensor:
+        """``what`` = 'fwd', 'adj' or 'fbp' over a host-resident stack of whole
+        chunks, the plan describing one chunk: chunk i is copied to the device
+        while chunk i-1 is computed and chunk i-2 copied back.  ``host_in`` is a
+        float32 CPU tensor holding n_chunks chunks (pinned memory for the copies
+        to overlap); ``host_out`` (allocated pinned when None) receives the
+        results.  With ``sync`` the call waits until ``host_out`` is complete."""
+        codes = {"fwd": NR_STREAM_FWD, "adj": NR_STREAM_ADJ, "fbp": NR_STREAM_FBP}
+        if what not in codes:
+            raise ValueError(f"what must be one of {sorted(codes)}")
+        fcodes = {"ramp": NR_FBP_RAMP, "butterworth": NR_FBP_BUTTERWORTH}
+        if filter not in fcodes:
+            raise ValueError(f"filter must be one of {sorted(fcodes)}")
+        n_in, n_out = (self.vol_numel, self.sino_numel) if what == "fwd" else (self.sino_numel, self.vol_numel)
+        if host_in.device.type != "cpu" or host_in.dtype != torch.float32 or not host_in.is_contiguous():
+            raise ValueError("host_in must be a contiguous float32 CPU tensor")
+        if host_in.numel() % n_in:
+            raise ValueError(f"host_in has {host_in.numel()} elements, not a multiple of the chunk's {n_in}")
+        n_chunks = host_in.numel() // n_in
+        if host_out is None:
+            host_out = torch.empty(n_chunks * n_out, dtype=torch.float32, pin_memory=True)
+        if (host_out.device.type != "cpu" or host_out.dtype != torch.float32 or not host_out.is_contiguous()
+                or host_out.numel() != n_chunks * n_out):
+            raise ValueError(f"host_out must be a contiguous float32 CPU tensor of {n_chunks * n_out} elements")
+        key = (n_in, n_out)
+        if getattr(self, "_stream_key", None) != key:
+            self._stream_bufs = [torch.empty(n, dtype=torch.float32, device=self.device)
+                                 for n in (n_in, n_in, n_out, n_out)]
+            self._stream_key = key
+        bufs = self._stream_bufs
+        d_in = (ctypes.c_void_p * 2)(bufs[0].data_ptr(), bufs[1].data_ptr())
+        d_out = (ctypes.c_void_p * 2)(bufs[2].data_ptr(), bufs[3].data_ptr())
+        params = NrFbp(fcodes[filter], int(order), float(cutoff))
+        with torch.cuda.device(self.device):
+            check(lib().radon_stream(self._h, codes[what], ctypes.byref(params), ctypes.c_void_p(host_in.data_ptr()),
+                                     ctypes.c_void_p(host_out.data_ptr()), n_chunks, d_in, d_out,
+                                     _stream(self.device)), "radon_stream")
+            if sync:
+                torch.cuda.current_stream(self.device).synchronize()
+        return host_out
 
     def normal(self, vol: torch.Tensor, b: torch.Tensor | None = None, sino: torch.Tensor | None = None,
                out: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
@@ -450,6 +493,35 @@ class MBIR:
     @property
     def nonfinite(self) -> bool:
         return bool(self.state[2].item() != 0.0)
+
+
+def stream_stack(what: str, host_in: torch.Tensor, n: int, n_det: int, angles, chunk: int, center: float = 0.0,
+                 device: torch.device | str | None = None, filter: str = "ramp", order: int = 2,
+                 cutoff: float = 0.25, tuning: dict | None = None) -> torch.Tensor:
+    """``what`` = 'fwd', 'adj' or 'fbp' over a host-resident uniform stack of Z
+    slices, streamed through the GPU ``chunk`` slices at a time (``Plan.stream``);
+    a last, shorter chunk runs on a plan of its own.  Returns a pinned CPU
+    tensor ``[Z, n_angles, n_det]`` (fwd) or ``[Z, n, n]``."""
+    ang = np.asarray(angles, dtype=np.float64)
+    na = len(ang)
+    fwd = what == "fwd"
+    per_in, per_out = (n * n, na * n_det) if fwd else (na * n_det, n * n)
+    if chunk < 1:
+        raise ValueError("chunk must be >= 1")
+    if host_in.numel() % per_in:
+        raise ValueError(f"host_in has {host_in.numel()} elements, not a whole number of slices of {per_in}")
+    Z = host_in.numel() // per_in
+    host_out = torch.empty((Z, na, n_det) if fwd else (Z, n, n), dtype=torch.float32, pin_memory=True)
+    flat_in, flat_out = host_in.reshape(-1), host_out.view(-1)
+    full, tail = divmod(Z, chunk)
+    kw = dict(filter=filter, order=order, cutoff=cutoff)
+    for count, z0, k in ((chunk, 0, full), (tail, full * chunk, 1 if tail else 0)):
+        if k == 0:
+            continue
+        plan = Plan.uniform_stack(n, n_det, ang, count, center=center, device=device, tuning=tuning)
+        plan.stream(what, flat_in[z0 * per_in:(z0 + k * count) * per_in],
+                    flat_out[z0 * per_out:(z0 + k * count) * per_out], **kw)
+    return host_out
 
 
 def power_lipschitz(plan: Plan, iters: int = 30, seed: int = 0, safety: float = 1.01) -> float:

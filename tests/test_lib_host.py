@@ -104,6 +104,9 @@ def test_plan_validation_status_codes(L):
     assert L.radon_fwd(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == _lib.NR_INVALID_ARG  # not bound
     ramp = _lib.NrFbp(_lib.NR_FBP_RAMP, 0, 0.0)
     assert L.radon_fbp(h, ctypes.byref(ramp), ctypes.c_void_p(8), ctypes.c_void_p(8), None) == _lib.NR_INVALID_ARG
+    bufs = (ctypes.c_void_p * 2)(8, 16)
+    assert L.radon_stream(h, _lib.NR_STREAM_FWD, None, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, bufs, bufs,
+                          None) == _lib.NR_INVALID_ARG
     L.nr_plan_destroy(h)
 
 
