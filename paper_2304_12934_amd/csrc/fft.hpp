@@ -348,6 +348,38 @@ __device__ __forceinline__ void fft_lds(Lds s, TwPtr __restrict__ tw, int tid) {
   fft_passes<L, T, INV>(s, tw, tid);
 }
 
+// Forward or inverse transform of a length-L/2 signal zero-padded to L and
+// centred, i.e. non-zero only at natural indices [0, L/4) and [3L/4, L).
+// The first pass takes its inputs from load(n) straight into registers (the
+// zero inputs of each of its butterflies sit at fixed positions) and writes
+// the LDS buffer; the remaining passes run as in fft_lds.  No LDS fill or
+// zero padding precedes it; on return s holds the result and the workgroup
+// has synchronised.
+template <int L, int T, bool INV, class Load>
+__device__ __forceinline__ void fft_lds_halfzero(Lds s, TwPtr __restrict__ tw, int tid, Load&& load) {
+  static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
+  constexpr int R = radix_of(L, 0);
+  static_assert(R % 4 == 0 && L % 4 == 0, "the first radix must split the zero padding evenly");
+  constexpr int NB = L / R;
+  constexpr int PER = (NB + T - 1) / T;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = tid + i * T;
+    if (NB % T == 0 || j < NB) {
+      // input r of butterfly j is index j + r NB: below L/4 for r < R/4, at
+      // or above 3L/4 for r >= 3R/4, padding in between
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = (r < R / 4 || r >= 3 * R / 4) ? load(j + r * NB) : make_float2(0.f, 0.f);
+      Dft<R, INV>::run(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[j * R + r] = v[r];
+    }
+  }
+  __syncthreads();
+  fft_passes<L, T, INV, 1>(s, tw, tid);
+}
+
 // threads per transform for a length-L FFT.  For 5·2^a lengths five
 // wavefronts split the radix-8 and radix-4 passes evenly (2560: 320 radix-8
 // butterflies per pass; 5120: 640 and 1280), where four would leave the last

@@ -236,13 +236,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(LaunchArgs a) {
     const float* __restrict__ f0 = a.vol_in + d.vol_off + size_t(iy0) * N;
     const float d0 = d.deapod[iy0], d1 = d.deapod[iy0 + 1];
     // x = ix - N/2 sits at index x mod L; indices N/2 .. L - N/2 - 1 are the zero padding
-    NR_STRIDED(ix, N, T) {
-      const float dx = d.deapod[ix];
-      s[ix < N / 2 ? ix + L - N / 2 : ix - N / 2] = make_float2(dx * d0 * f0[ix], dx * d1 * f0[N + ix]);
-    }
-    NR_STRIDED(k, N, T) s[N / 2 + k] = make_float2(0.f, 0.f);
-    __syncthreads();
-    fft_lds<L, T, false>(s, d.tw_G, tid);
+    const NR_G float* __restrict__ dp = d.deapod;
+    fft_lds_halfzero<L, T, false>(s, d.tw_G, tid, [&](int n) {
+      const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+      const float dx = dp[ix];
+      return make_float2(dx * d0 * f0[ix], dx * d1 * f0[N + ix]);
+    });
     // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
     NR_G float4* __restrict__ out = (NR_G float4*)d.T;
     NR_STRIDED(q, L / 2 + 1, T) {
@@ -283,16 +282,13 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
     constexpr int N = L / 2;   // G = 2N
     const int cols = d.cols;
     const int qx = wi.unit;
-    const NR_G float4* __restrict__ T4 = (const NR_G float4*)d.T;
-    NR_STRIDED(pp, N / 2, T) {
-      const float4 v = T4[t4(qx, pp, N)];
-      const int iy = 2 * pp, iy1 = iy + 1;
-      s[iy < N / 2 ? iy + L - N / 2 : iy - N / 2] = make_float2(v.x, v.y);
-      s[iy1 < N / 2 ? iy1 + L - N / 2 : iy1 - N / 2] = make_float2(v.z, v.w);
-    }
-    NR_STRIDED(k, N, T) s[N / 2 + k] = make_float2(0.f, 0.f);
-    __syncthreads();
-    fft_lds<L, T, false>(s, d.tw_G, tid);
+    // y = iy - N/2 sits at index y mod L; row iy of column qx is half iy & 1
+    // of the tile entry t4(qx, iy / 2)
+    const NR_G float2* __restrict__ T2 = (const NR_G float2*)d.T;
+    fft_lds_halfzero<L, T, false>(s, d.tw_G, tid, [&](int n) {
+      const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+      return T2[2 * t4(qx, iy >> 1, N) + (iy & 1)];
+    });
     NR_G float2* ext = d.ext;
     NR_G float2* row = ext + size_t(qx + halo) * cols;
     // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
