@@ -330,11 +330,11 @@ __device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) 
   __syncthreads();
 }
 
-template <int L, int T, bool INV, int P = 0>
+template <int L, int T, bool INV, int P = 0, int END = num_passes(L)>
 __device__ __forceinline__ void fft_passes(Lds s, TwPtr __restrict__ tw, int tid) {
-  if constexpr (P < num_passes(L)) {
+  if constexpr (P < END) {
     fft_pass<L, T, P, INV>(s, tw, tid);
-    fft_passes<L, T, INV, P + 1>(s, tw, tid);
+    fft_passes<L, T, INV, P + 1, END>(s, tw, tid);
   }
 }
 
@@ -378,6 +378,45 @@ __device__ __forceinline__ void fft_lds_halfzero(Lds s, TwPtr __restrict__ tw, i
   }
   __syncthreads();
   fft_passes<L, T, INV, 1>(s, tw, tid);
+}
+
+// Transform of which only the outputs at natural indices [0, L/4) and
+// [3L/4, L) are wanted (the centred half of a length-L result).  All passes
+// but the last run as in fft_lds; the last one hands each wanted output
+// straight from registers to store(n, value) instead of writing the LDS
+// buffer.  Expects s filled and the workgroup synchronised; leaves s holding
+// the input of the last pass, and the caller must synchronise before
+// writing s again.
+template <int L, int T, bool INV, class Store>
+__device__ __forceinline__ void fft_lds_halfout(Lds s, TwPtr __restrict__ tw, int tid, Store&& store) {
+  static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
+  constexpr int P = num_passes(L) - 1;
+  constexpr int R = radix_of(L, P);
+  constexpr int Ns = span_before(L, P);
+  static_assert(Ns * R == L && P >= 1, "a transform of at least two passes");
+  fft_passes<L, T, INV, 0, P>(s, tw, tid);
+  constexpr int PER = (Ns + T - 1) / T;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    // butterfly j of the last pass reads j + r Ns and yields outputs j + r Ns
+    const int j = tid + i * T;
+    if (Ns % T == 0 || j < Ns) {
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = s[j + r * Ns];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[r * j];
+        v[r] = c_mul(v[r], INV ? c_conj(w) : w);
+      }
+      Dft<R, INV>::run(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n = j + r * Ns;
+        if (n < L / 4 || n >= L - L / 4) store(n, v[r]);
+      }
+    }
+  }
 }
 
 // threads per transform for a length-L FFT.  For 5·2^a lengths five

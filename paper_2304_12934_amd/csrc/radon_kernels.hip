@@ -797,12 +797,13 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
       }
     }
     __syncthreads();
-    fft_lds<L, T, true>(s, d.tw_G, tid);
-    NR_G float4* __restrict__ T4 = (NR_G float4*)d.T;
-    NR_STRIDED(pp, N / 2, T) {
-      const float2 a0 = s[wrap_index<L>(2 * pp - N / 2)], a1 = s[wrap_index<L>(2 * pp + 1 - N / 2)];
-      T4[t4(qx, pp, N)] = make_float4(a0.x, a0.y, a1.x, a1.y);
-    }
+    // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
+    // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
+    NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
+    fft_lds_halfout<L, T, true>(s, d.tw_G, tid, [&](int n, float2 v) {
+      const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+      T2[2 * t4(qx, iy >> 1, N) + (iy & 1)] = v;
+    });
     __syncthreads();
   }
 }
@@ -834,15 +835,16 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
       if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
     }
     __syncthreads();
-    fft_lds<L, T, true>(s, d.tw_G, tid);
     const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
     float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
-    NR_STRIDED(ix, N, T) {
-      const float2 z = s[wrap_index<L>(ix - N / 2)];
-      const float dx = d.deapod[ix];
+    const NR_G float* __restrict__ dp = d.deapod;
+    // x = ix - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and [L - N/2, L)
+    fft_lds_halfout<L, T, true>(s, d.tw_G, tid, [&](int n, float2 z) {
+      const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+      const float dx = dp[ix];
       g0[ix] = dx * d0 * z.x;
       g0[N + ix] = dx * d1 * z.y;
-    }
+    });
     __syncthreads();
   }
 }
