@@ -348,53 +348,63 @@ __device__ __forceinline__ void fft_lds(Lds s, TwPtr __restrict__ tw, int tid) {
   fft_passes<L, T, INV>(s, tw, tid);
 }
 
-// Forward or inverse transform of a length-L/2 signal zero-padded to L and
-// centred, i.e. non-zero only at natural indices [0, L/4) and [3L/4, L).
-// The first pass takes its inputs from load(n) straight into registers (the
-// zero inputs of each of its butterflies sit at fixed positions) and writes
-// the LDS buffer; the remaining passes run as in fft_lds.  No LDS fill or
-// zero padding precedes it; on return s holds the result and the workgroup
-// has synchronised.
-template <int L, int T, bool INV, class Load>
-__device__ __forceinline__ void fft_lds_halfzero(Lds s, TwPtr __restrict__ tw, int tid, Load&& load) {
-  static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
+// First pass of a transform whose inputs come from load(n) (natural index
+// n) straight into registers; the pass writes the LDS buffer and the
+// workgroup synchronises.  With HALF, the input is a length-L/2 signal
+// zero-padded to L and centred (non-zero only at natural indices [0, L/4)
+// and [3L/4, L)): the zeros of each first-pass butterfly sit at fixed
+// positions and are not loaded.
+template <int L, int T, bool INV, bool HALF, class Load>
+__device__ __forceinline__ void fft_first_pass_from(Lds s, int tid, Load&& load) {
   constexpr int R = radix_of(L, 0);
-  static_assert(R % 4 == 0 && L % 4 == 0, "the first radix must split the zero padding evenly");
+  static_assert(!HALF || (R % 4 == 0 && L % 4 == 0), "the first radix must split the zero padding evenly");
   constexpr int NB = L / R;
   constexpr int PER = (NB + T - 1) / T;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = tid + i * T;
     if (NB % T == 0 || j < NB) {
-      // input r of butterfly j is index j + r NB: below L/4 for r < R/4, at
-      // or above 3L/4 for r >= 3R/4, padding in between
+      // input r of butterfly j is index j + r NB: with HALF, below L/4 for
+      // r < R/4, at or above 3L/4 for r >= 3R/4, padding in between
       float2 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = (r < R / 4 || r >= 3 * R / 4) ? load(j + r * NB) : make_float2(0.f, 0.f);
+      for (int r = 0; r < R; ++r)
+        v[r] = (!HALF || r < R / 4 || r >= 3 * R / 4) ? load(j + r * NB) : make_float2(0.f, 0.f);
       Dft<R, INV>::run(v);
 #pragma unroll
       for (int r = 0; r < R; ++r) s[j * R + r] = v[r];
     }
   }
   __syncthreads();
+}
+
+// Transform of a length-L/2 signal zero-padded to L and centred, its input
+// from load(n): the first pass as fft_first_pass_from with HALF, the rest as
+// in fft_lds.  No LDS fill precedes it; on return s holds the result and the
+// workgroup has synchronised.
+template <int L, int T, bool INV, class Load>
+__device__ __forceinline__ void fft_lds_halfzero(Lds s, TwPtr __restrict__ tw, int tid, Load&& load) {
+  static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
+  fft_first_pass_from<L, T, INV, true>(s, tid, load);
   fft_passes<L, T, INV, 1>(s, tw, tid);
 }
 
 // Transform of which only the outputs at natural indices [0, L/4) and
-// [3L/4, L) are wanted (the centred half of a length-L result).  All passes
-// but the last run as in fft_lds; the last one hands each wanted output
-// straight from registers to store(n, value) instead of writing the LDS
-// buffer.  Expects s filled and the workgroup synchronised; leaves s holding
-// the input of the last pass, and the caller must synchronise before
+// [3L/4, L) are wanted (the centred half of a length-L result).  Passes
+// START to the last but one run as in fft_lds (START = 1 after
+// fft_first_pass_from); the last one hands each wanted output straight from
+// registers to store(n, value) instead of writing the LDS buffer.  Expects s
+// to hold the input of pass START and the workgroup synchronised; leaves s
+// holding the input of the last pass, and the caller must synchronise before
 // writing s again.
-template <int L, int T, bool INV, class Store>
+template <int L, int T, bool INV, int START = 0, class Store>
 __device__ __forceinline__ void fft_lds_halfout(Lds s, TwPtr __restrict__ tw, int tid, Store&& store) {
   static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
   constexpr int P = num_passes(L) - 1;
   constexpr int R = radix_of(L, P);
   constexpr int Ns = span_before(L, P);
-  static_assert(Ns * R == L && P >= 1, "a transform of at least two passes");
-  fft_passes<L, T, INV, 0, P>(s, tw, tid);
+  static_assert(Ns * R == L && P >= 1 && START <= P, "a transform of at least two passes");
+  fft_passes<L, T, INV, START, P>(s, tw, tid);
   constexpr int PER = (Ns + T - 1) / T;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {

@@ -783,24 +783,25 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
     const NR_G float2* row = ext + size_t(qx + halo) * cols;
     const NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
     const NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    NR_STRIDED(n, L, T) s[n] = row[wrap_index<L>(n + L / 2) + colpad];
-    // the periodic copies (n within colpad of L/2) and, for the columns next to
-    // qx = 0 and G/2, the conjugate mirror rows; each thread revisits its own n
-    NR_STRIDED(n, L, T) {
-      const int p = wrap_index<L>(n + L / 2) + colpad;
-      if (m1 || m2 || p >= L || p < 2 * colpad) {
-        float2 v = load_folded<L>(row, colpad, n);
-        const int nm = n == 0 ? 0 : L - n;
-        if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
-        if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
-        s[n] = v;
-      }
-    }
-    __syncthreads();
+    // natural index n (q_y = n, or n - L from L/2 on) gathers the cell, its
+    // periodic copies (n within colpad of L/2) and, for the columns next to
+    // qx = 0 and G/2, the conjugate mirror rows.  Nothing is spread farther
+    // than rdisc from the origin (nor onto any copy of such a cell), so those
+    // cells are zero and not read.
+    const int r2 = d.rdisc * d.rdisc - qx * qx;
+    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+      const int qy = n < L / 2 ? n : n - L;
+      if (qy * qy > r2) return make_float2(0.f, 0.f);
+      float2 v = load_folded<L>(row, colpad, n);
+      const int nm = n == 0 ? 0 : L - n;
+      if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+      if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+      return v;
+    });
     // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
     // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
     NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
-    fft_lds_halfout<L, T, true>(s, d.tw_G, tid, [&](int n, float2 v) {
+    fft_lds_halfout<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 v) {
       const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
       T2[2 * t4(qx, iy >> 1, N) + (iy & 1)] = v;
     });
