@@ -389,16 +389,16 @@ __device__ __forceinline__ void fft_lds_halfzero(Lds s, TwPtr __restrict__ tw, i
   fft_passes<L, T, INV, 1>(s, tw, tid);
 }
 
-// Transform of which only the outputs at natural indices [0, L/4) and
-// [3L/4, L) are wanted (the centred half of a length-L result).  Passes
-// START to the last but one run as in fft_lds (START = 1 after
-// fft_first_pass_from); the last one hands each wanted output straight from
-// registers to store(n, value) instead of writing the LDS buffer.  Expects s
-// to hold the input of pass START and the workgroup synchronised; leaves s
-// holding the input of the last pass, and the caller must synchronise before
-// writing s again.
-template <int L, int T, bool INV, int START = 0, class Store>
-__device__ __forceinline__ void fft_lds_halfout(Lds s, TwPtr __restrict__ tw, int tid, Store&& store) {
+// Transform whose last pass hands its outputs straight from registers to
+// store(n, value) (natural index n) instead of writing the LDS buffer; with
+// HALF only the outputs at [0, L/4) and [3L/4, L) (the centred half of the
+// result) are handed over.  Passes START to the last but one run as in
+// fft_lds (START = 1 after fft_first_pass_from).  Expects s to hold the
+// input of pass START and the workgroup synchronised; leaves s holding the
+// input of the last pass, and the caller must synchronise before writing s
+// again.
+template <int L, int T, bool INV, int START = 0, bool HALF = true, class Store>
+__device__ __forceinline__ void fft_lds_store_out(Lds s, TwPtr __restrict__ tw, int tid, Store&& store) {
   static_assert(radix_plan_complete(L), "FFT length must be 2^a * 3^b * 5^c");
   constexpr int P = num_passes(L) - 1;
   constexpr int R = radix_of(L, P);
@@ -423,7 +423,7 @@ __device__ __forceinline__ void fft_lds_halfout(Lds s, TwPtr __restrict__ tw, in
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int n = j + r * Ns;
-        if (n < L / 4 || n >= L - L / 4) store(n, v[r]);
+        if (!HALF || n < L / 4 || n >= L - L / 4) store(n, v[r]);
       }
     }
   }

@@ -285,7 +285,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
     // y = iy - N/2 sits at index y mod L; row iy of column qx is half iy & 1
     // of the tile entry t4(qx, iy / 2)
     const NR_G float2* __restrict__ T2 = (const NR_G float2*)d.T;
-    fft_lds_halfzero<L, T, false>(s, d.tw_G, tid, [&](int n) {
+    fft_first_pass_from<L, T, false, true>(s, tid, [&](int n) {
       const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
       return T2[2 * t4(qx, iy >> 1, N) + (iy & 1)];
     });
@@ -294,9 +294,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
     // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
     NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
     NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+    fft_passes<L, T, false, 1>(s, d.tw_G, tid);
     // only |q| <= rdisc is ever read: the natural indices n in [0, lim] and
     // [L - lim, L) of this row (a cell's periodic copies lie farther out than
-    // the cell itself, and mirror rows keep |q_y|)
+    // the cell itself, and mirror rows keep |q_y|).  Stored from LDS by every
+    // thread: measured faster than storing from the last pass's registers,
+    // which for L = 5120 leaves a fifth of the threads idle.
     const int r2 = d.rdisc * d.rdisc - qx * qx;
     const int lim = r2 <= 0 ? -1 : int(sqrtf(float(r2)));
     const bool full = lim >= L / 2;   // the whole row, q_y = -L/2 included
@@ -801,7 +804,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
     // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
     // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
     NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
-    fft_lds_halfout<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 v) {
+    fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 v) {
       const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
       T2[2 * t4(qx, iy >> 1, N) + (iy & 1)] = v;
     });
@@ -824,23 +827,24 @@ __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
     constexpr int N = L / 2;   // G = 2N
     const int iy0 = 2 * wi.unit;
     const NR_G float4* __restrict__ in = (const NR_G float4*)d.T;
-    // Hermitian completion with doubled real parts at q = 0 and G/2, two rows packed
-    NR_STRIDED(q, L / 2 + 1, T) {
+    // Hermitian completion with doubled real parts at q = 0 and G/2, two rows
+    // packed: index n <= L/2 takes entry q = n as X + iY, index L - q the
+    // conjugate-symmetric combination of the same entry
+    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+      const int q = n <= L / 2 ? n : L - n;
       const float4 t = in[t4(q, iy0 >> 1, N)];
       float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
       if (q == 0 || q == L / 2) {
         X = make_float2(2.f * X.x, 0.f);
         Y = make_float2(2.f * Y.x, 0.f);
       }
-      s[q] = make_float2(X.x - Y.y, X.y + Y.x);
-      if (q > 0 && q < L / 2) s[L - q] = make_float2(X.x + Y.y, Y.x - X.y);
-    }
-    __syncthreads();
+      return n <= L / 2 ? make_float2(X.x - Y.y, X.y + Y.x) : make_float2(X.x + Y.y, Y.x - X.y);
+    });
     const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
     float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
     const NR_G float* __restrict__ dp = d.deapod;
     // x = ix - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and [L - N/2, L)
-    fft_lds_halfout<L, T, true>(s, d.tw_G, tid, [&](int n, float2 z) {
+    fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 z) {
       const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
       const float dx = dp[ix];
       g0[ix] = dx * d0 * z.x;
