@@ -153,6 +153,12 @@ double KaiserBessel::max_poly_error() const {
 // spreading bins
 // ---------------------------------------------------------------------------
 
+int disc_radius(const Plan& plan, const Geom& g) {
+  // the polar points reach |u| = (N_t/2)(G/N_t) = G/2 cells; their taps
+  // W/2 cells further (one cell of margin on top)
+  return g.G / 2 + (plan.kb.W + 1) / 2 + 2;
+}
+
 void build_spread_bins(const Plan& plan, Geom& g) {
   const int W = plan.kb.W;
   const int na = g.key.n_angles;
@@ -198,11 +204,28 @@ void build_spread_bins(const Plan& plan, Geom& g) {
   const int dc0 = d0 + g.G / 2 + plan.colpad, dc1 = dc0 + W - 1;
   g.items.clear();
   g.zero_tiles.clear();
+  // The adjoint column transform reads only cells whose natural frequency
+  // (mirror rows folded back, periodic columns wrapped) lies within rdisc of
+  // the origin.  A tile without points and without such a cell is neither
+  // written nor read, so it gets no work item.
+  const int64_t rd2 = int64_t(disc_radius(plan, g)) * disc_radius(plan, g);
+  auto unread = [&](int ty, int tx) {
+    for (int r = ty * g.tile_h; r < std::min(g.rows, (ty + 1) * g.tile_h); ++r) {
+      int qx = r - plan.halo;
+      qx = qx < 0 ? -qx : (qx > g.G / 2 ? g.G - qx : qx);
+      for (int c = tx * g.tile_w; c < std::min(g.cols, (tx + 1) * g.tile_w); ++c) {
+        const int qy = ((c - plan.colpad) % g.G + g.G) % g.G - g.G / 2;
+        if (int64_t(qx) * qx + int64_t(qy) * qy <= rd2) return false;
+      }
+    }
+    return true;
+  };
   std::vector<int32_t> cell_count(size_t(g.tile_w) * g.tile_h);
   for (int t = 0; t < ntiles; ++t) {
     const int b = g.tile_start[t], e = g.tile_start[t + 1];
-    const int n_items = std::max(1, (e - b + chunk - 1) / chunk);
     const int ty = t / g.tiles_x, tx = t % g.tiles_x;
+    if (e == b && unread(ty, tx)) continue;
+    const int n_items = std::max(1, (e - b + chunk - 1) / chunk);
     const bool has_dc = ty * g.tile_h <= dr1 && (ty + 1) * g.tile_h > dr0 &&
                         tx * g.tile_w <= dc1 && (tx + 1) * g.tile_w > dc0;
     if (n_items > 1) g.zero_tiles.push_back(t);
@@ -666,9 +689,7 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.items = reinterpret_cast<const SpreadItem*>(d_ws + g.off_items);
       d.zero_tiles = reinterpret_cast<const int32_t*>(d_ws + g.off_zero);
       d.itiles_x = g.itiles_x;
-      // the polar points reach |u| = (N_t/2)(G/N_t) = G/2 cells; their taps
-      // W/2 cells further (one cell of margin on top)
-      d.rdisc = g.G / 2 + (plan.kb.W + 1) / 2 + 2;
+      d.rdisc = disc_radius(plan, g);
       d.ipts = reinterpret_cast<const int32_t*>(d_ws + g.off_ipts);
       d.iitems = reinterpret_cast<const SpreadItem*>(d_ws + g.off_iitems);
       out[size_t(s)] = d;

@@ -155,6 +155,10 @@ nr_status layout_plan(Plan& plan, std::string& err);
 // Per-slice descriptors with absolute pointers into the workspace at d_ws.
 std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws);
 
+// Radius (grid cells, from the origin of the spectrum) beyond which no
+// spreading tap lands and no interpolation tap reads.
+int disc_radius(const Plan& plan, const Geom& g);
+
 // Fills the spreading bins of one geometry (called by layout_plan).
 void build_spread_bins(const Plan& plan, Geom& g);
 
