@@ -83,3 +83,27 @@ def test_2048_forward_and_adjoint_sampled():
     e = rel(g, ora.radon_adj(y[sample], ang[sample], n))
     print(f"2048 adj rel L2: {e:.3e}", flush=True)
     assert e < TOL
+
+
+@pytest.mark.parametrize("n,nd,na,sample", [(4096, 4096, 96, [0, 47]), (1024, 8192, 64, [5, 40])])
+def test_largest_transform_lengths_sampled(n, nd, na, sample):
+    """The longest built FFT length, 8192: as the grid transform (4096^2 slices,
+    G = 8192) and as the radial transform (8192 detector bins)."""
+    from paper_2304_12934_amd import Plan
+    print(f"case: {n}^2, {nd} bins, {na} angles, sampled fwd/adj", flush=True)
+    dev = torch.device("cuda", 0)
+    ang = synth.uniform_angles(na)
+    f = synth.ellipse_phantom(2, 7, n, 20).numpy()
+    plan = Plan.uniform_stack(n, nd, ang, 1, device=dev)
+    sample = np.array(sample)
+    s = plan.fwd(torch.as_tensor(f[None], dtype=torch.float32, device=dev)).cpu().numpy()[0]
+    e = rel(s[sample], ora.radon_fwd(f, ang[sample], nd))
+    print(f"fwd rel L2: {e:.3e}", flush=True)
+    assert e < TOL
+    assert np.abs(s.astype(np.float64).sum(axis=1) - f.sum()).max() / f.sum() < TOL
+    y = np.zeros((na, nd))
+    y[sample] = np.random.default_rng(9).standard_normal((len(sample), nd))
+    g = plan.adj(torch.as_tensor(y[None], dtype=torch.float32, device=dev)).cpu().numpy()[0]
+    e = rel(g, ora.radon_adj(y[sample], ang[sample], n))
+    print(f"adj rel L2: {e:.3e}", flush=True)
+    assert e < TOL
