@@ -180,6 +180,54 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
     return out
 
 
+# The paper's end-to-end timings (Sec. 5, Table "tab:runtimes": tomoCAM MBIR,
+# 100 iterations, one machine with 4x Tesla P100 and 2x Xeon E5-2620 v4, data
+# streamed from host memory) for the shapes that this projector supports; the
+# 2448-wide dataset needs radix-17 transforms and is left out.
+PAPER_SHAPES = (
+    ("foam phantom", 2048, 16, 128, 93.0),
+    ("TB-25", 2048, 128, 400, 862.0),
+)
+
+
+def paper_shapes_leg(dev, iters: int = 100) -> list:
+    """100 plain MBIR iterations at the paper's dataset shapes (slices x N^2,
+    angles), on synthetic ellipsoid volumes with Poisson data standing in for
+    the paper's data, with the volume resident in HBM.  Context beside the
+    paper's timings, not a target: different hardware, data and stopping."""
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import MBIR, Plan, Prior, power_lipschitz
+
+    out = []
+    for name, n, nz, na, paper_s in PAPER_SHAPES:
+        vol = synth.ellipsoid_volume(6, n, nz, 20, device=dev).to(torch.float32).contiguous()
+        plan = Plan.uniform_stack(n, n, synth.uniform_angles(na), nz, device=dev)
+        b_true = plan.fwd(vol)
+        scale = 2.0 / float(b_true.max())
+        b_true *= scale
+        b = torch.as_tensor(synth.poisson_log_data(b_true, synth.rng_for(6, nz), 1.0e4), dtype=torch.float32,
+                            device=dev).contiguous()
+        del vol, b_true
+        prior = Prior(lam=1.0)
+        L = power_lipschitz(plan, 30) + prior.lipschitz()
+        m = MBIR(plan, b, prior, L)
+        m.step()
+        m = MBIR(plan, b, prior, L)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.run(iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.append({"dataset_shape": name, "slices": nz, "n": n, "n_angles": na, "iterations": iters,
+                    "seconds": round(dt, 3), "slice_iters_per_s": round(nz * iters / dt, 1),
+                    "paper_seconds": paper_s, "paper_hardware": "4x Tesla P100, 2x Xeon E5-2620 v4"})
+        del m, plan, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(dev, count: int, reps: int) -> dict:
     """Uneven stack: `count` slices with N in {512, 1024, 2048}, angle counts
     U[128, 1500] (half sparse with a random offset, half limited-view), N_t = N.
@@ -244,6 +292,8 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
     ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-stack leg")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the 100-iteration MBIR runs at the paper's dataset shapes")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the filtered back-projection and rotation-axis offset timings")
     ap.add_argument("--batched-slices", type=int, default=96)
@@ -437,6 +487,13 @@ def main() -> int:
         mbir = mbir_leg(dev, args.mbir_n, args.mbir_slices, args.mbir_angles, args.mbir_iters, 10)
         print(f"[bench] MBIR {mbir}", file=sys.stderr, flush=True)
 
+    paper = None
+    if not args.no_paper_shapes:
+        torch.cuda.empty_cache()
+        print("[bench] paper-shape MBIR leg ...", file=sys.stderr, flush=True)
+        paper = paper_shapes_leg(dev)
+        print(f"[bench] paper shapes {paper}", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         torch.cuda.empty_cache()
@@ -480,6 +537,7 @@ def main() -> int:
         "stages": stage_report,
         "mbir": mbir,
         "uneven_stack": batched,
+        "paper_shapes_mbir": paper,
         "extensions": extensions,
         "wall_s": round(wall, 3),
         "git": sha,
