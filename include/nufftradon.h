@@ -147,7 +147,7 @@ nr_status nr_plan_destroy(nr_plan* plan);
  *                       one 2560^2 slice, whose grids then stay in the 256 MB
  *                       last-level cache between stages; a slice larger than
  *                       the budget runs alone)
- *   "streams"           1..8 (3 default): batches run round-robin on this many
+ *   "streams"           1..8 (2 default): batches run round-robin on this many
  *                       streams the plan owns (forked from and joined back to
  *                       the caller's stream on every call), each with its own
  *                       scratch, so that the stages of different batches

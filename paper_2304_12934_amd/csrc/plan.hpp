@@ -88,7 +88,7 @@ struct Tuning {
   int batch_mb = 160;             // scratch budget of one batch in MiB (a lone slice may exceed it)
   int spread_mode = 0;            // 0: LDS tiles, 1: global atomics (reference)
   int interp_mode = 0;            // 0: LDS tiles + radial pass, 1: direct gathers per angle pair
-  int streams = 3;                // batches run round-robin on this many concurrent streams
+  int streams = 2;                // batches run round-robin on this many concurrent streams
 };
 
 // Stages of the forward chain (FwdRows, FwdCols, FwdInterp, FwdRadial) and of the
