@@ -67,21 +67,23 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(stage: str, n: int, na: int) -> float | None:
+def measured_traffic(stage: str, n: int, na: int, per_launch: float) -> float | None:
     """HBM bytes of one launch of `stage` from the committed counter summary.
 
     The summary holds FETCH_SIZE and WRITE_SIZE per dispatch (rocprofv3
     --pmc), each scaled by what the same counter reads for a device copy of
-    known size, for one workload and one version of the kernel sources; None
-    when the workload or the sources differ.
+    known size, for one workload, one number of slices per launch and one
+    version of the kernel sources; None when any of them differs.
     """
     if (n, na) != (2560, 1024) or not os.path.exists(TRAFFIC_FILE):
         return None
-    digest, rows = None, {}
+    digest, rows, slices = None, {}, None
     with open(TRAFFIC_FILE) as fh:
         for line in fh:
             if line.startswith("source digest:"):
                 digest = line.split(":", 1)[1].strip().strip("`")
+            if line.startswith("slices per launch:"):
+                slices = float(line.split(":", 1)[1])
             cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
             if len(cells) >= 5 and cells[0] in ("fwd_rows", "fwd_cols", "fwd_interp", "adj_radial", "spread",
                                                 "adj_cols", "adj_rows"):
@@ -89,7 +91,7 @@ def measured_traffic(stage: str, n: int, na: int) -> float | None:
                     rows[cells[0]] = float(cells[4])
                 except ValueError:
                     pass
-    if digest != kernel_source_digest():
+    if digest != kernel_source_digest() or slices != per_launch:
         return None
     return rows.get(stage)
 
@@ -305,7 +307,8 @@ def main() -> int:
     ap.add_argument("--tile-h", type=int, default=None, help="spreading tile height (plan tuning)")
     ap.add_argument("--chunk", type=int, default=None, help="points per spreading/interpolation item")
     ap.add_argument("--streams", type=int, default=None, help="concurrent streams of the plan (plan tuning)")
-    ap.add_argument("--batch-mb", type=int, default=None, help="scratch budget of one batch in MiB (plan tuning)")
+    ap.add_argument("--batch-mb", type=int, default=1400,
+                    help="scratch budget of one batch in MiB (plan tuning; 1400: eight 2560^2 slices per launch)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device-to-device copy of MIB MiB before timing (a counter reference)")
     args = ap.parse_args()
@@ -402,8 +405,8 @@ def main() -> int:
         per_ms = stages[dom][0] / (args.steps * max(1, info["batches"]))
         bytes_launch = sb[dom] * per_launch_slices
         achieved = bytes_launch / (per_ms * 1e-3) / 1e9
-        tb = measured_traffic(dom, n, na)
-        traffic = int(tb * per_launch_slices) if tb is not None else None
+        tb = measured_traffic(dom, n, na, per_launch_slices)
+        traffic = int(tb) if tb is not None else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "bytes_per_launch": int(bytes_launch), "ms_per_launch": round(per_ms, 5),
@@ -445,7 +448,10 @@ def main() -> int:
         SH = 3 * S
         h_vol = vol.cpu().repeat(3, 1, 1).pin_memory()
         h_sino = torch.empty(3 * plan.sino_numel, dtype=torch.float32, pin_memory=True)
-        plan_s = Plan.uniform_stack(n, nd, angles, chunk, device=dev, tuning=tuning or None)
+        # the chunk plan keeps the library's batch budget: one batch per slice,
+        # so its two streams overlap within a chunk
+        plan_s = Plan.uniform_stack(n, nd, angles, chunk, device=dev,
+                                    tuning={k: v for k, v in tuning.items() if k != "batch_mb"} or None)
 
         def host_rate(fn, k=2):
             fn()
