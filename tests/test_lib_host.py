@@ -91,6 +91,10 @@ def test_plan_validation_status_codes(L):
     bad[3] = np.nan
     assert _create(L, [(128, 128, 10, 0, 0, 0)], bad)[0] == _lib.NR_INVALID_ARG
     assert L.nr_last_error()
+    # an empty stack is refused (there is nothing to plan)
+    h0 = ctypes.c_void_p()
+    assert L.nr_plan_create(_slices((128, 128, 10, 0, 0, 0)), 0, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            None, ctypes.byref(h0)) == _lib.NR_INVALID_ARG
     # rotation-axis offset: finite and within half the detector
     assert _create(L, [(128, 128, 10, 0, 0, 0, float("nan"))], ang)[0] == _lib.NR_INVALID_ARG
     assert _create(L, [(128, 128, 10, 0, 0, 0, 64.5)], ang)[0] == _lib.NR_INVALID_ARG
