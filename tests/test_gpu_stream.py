@@ -118,3 +118,24 @@ def test_full_size_forward_stream(dev):
     got = plan4.stream("fwd", host.view(-1)).view(z, 1024, n)
     want = Plan.uniform_stack(n, n, ang, z, device=dev).fwd(vol).cpu()
     assert torch.equal(got, want)
+
+
+def test_uneven_chunk_plan(dev):
+    """A chunk of slices of different sizes, angle counts and axis offsets,
+    streamed three times over different data."""
+    from paper_2304_12934_amd import Plan, SliceGeometry
+    say("case: stream fwd/adj with an uneven 3-slice chunk, 3 chunks")
+    rng = np.random.default_rng(60)
+    geoms = [SliceGeometry(64, 64, rng.uniform(0, np.pi, 33), 0.0),
+             SliceGeometry(128, 160, rng.uniform(0, np.pi, 50), 2.5),
+             SliceGeometry(80, 80, rng.uniform(0, np.pi, 21), -1.0)]
+    plan = Plan(geoms, device=dev)
+    vols = rng.standard_normal((3, plan.vol_numel)).astype(np.float32)
+    sinos = rng.standard_normal((3, plan.sino_numel)).astype(np.float32)
+    s = plan.stream("fwd", torch.from_numpy(vols.reshape(-1)).pin_memory()).view(3, -1)
+    g = plan.stream("adj", torch.from_numpy(sinos.reshape(-1)).pin_memory()).view(3, -1)
+    for c in range(3):
+        want_s = plan.fwd(torch.as_tensor(vols[c], device=dev)).reshape(-1).cpu()
+        assert torch.equal(s[c], want_s)
+        want_g = plan.adj(torch.as_tensor(sinos[c], device=dev)).reshape(-1).cpu().numpy()
+        assert rel(g[c].numpy(), want_g) < 1e-6
