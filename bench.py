@@ -280,6 +280,14 @@ def batched_leg(dev, count: int, reps: int) -> dict:
             "launches_per_pass": info["launches"]}
 
 
+def ensure_built() -> None:
+    """Build the library only when none is there (bench loads what is built)."""
+    from paper_2304_12934_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2304_12934_amd import build
+        build.build(verbose=False)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +327,7 @@ def main() -> int:
               "the projector shards along z with no exchange, see the design notes", file=sys.stderr)
         return 2
 
+    ensure_built()
     import numpy as np
     import torch
 

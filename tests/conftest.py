@@ -10,6 +10,12 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    # the tests load the library that is built; only when none is there do
+    # they build it (the library itself never falls back to anything)
+    from paper_2304_12934_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2304_12934_amd import build
+        build.build(verbose=False)
 
 
 def _gpu_available() -> bool:
