@@ -398,9 +398,9 @@ class DataFidelityFn(torch.autograd.Function):
     def backward(ctx, g: torch.Tensor):
         (r,) = ctx.saved_tensors
         grad = ctx.plan.adj(r)
-        if g.numel() != 1 or float(g) != 1.0:
-            grad = grad * g.to(grad.dtype)
-        return grad, None, None
+        # scaled on the device whatever g is: testing g == 1 would stall the
+        # host until the forward has finished
+        return grad.mul_(g.to(grad.dtype)), None, None
 
 
 class QGGMRFFn(torch.autograd.Function):
@@ -479,11 +479,12 @@ class MBIR:
         if self.prior.lam > 0:
             loss = loss + QGGMRFFn.apply(y, self.prior)
         loss.backward()
-        self.grad.copy_(y.grad)
+        g = y.grad if y.grad.is_contiguous() else y.grad.contiguous()
         with torch.cuda.device(self.plan.device):
             check(lib().mbir_update(ctypes.byref(self.params), _ptr(self.x), _ptr(self.x_prev), _ptr(self.y),
-                                    _ptr(self.grad), self.x.numel(), _ptr(self.state), _stream(self.plan.device)),
+                                    _ptr(g), self.x.numel(), _ptr(self.state), _stream(self.plan.device)),
                   "mbir_update")
+        self.grad = g
         self.k += 1
 
     @property
