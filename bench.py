@@ -286,6 +286,28 @@ def batched_leg(dev, count: int, reps: int) -> dict:
             "launches_per_pass": info["launches"]}
 
 
+def device_copy_gbs(dev, stream, mib: int = 2048, reps: int = 5) -> float:
+    """Bytes read plus written per second by a plain device-to-device copy of
+    `mib` MiB (torch's copy kernel), timed with HIP events: the attainable
+    HBM rate that the dominant kernel is also compared against."""
+    import torch
+
+    src = torch.ones(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def ensure_built() -> None:
     """Build the library only when none is there (bench loads what is built)."""
     from paper_2304_12934_amd import _lib
@@ -422,10 +444,13 @@ def main() -> int:
         achieved = bytes_launch / (per_ms * 1e-3) / 1e9
         tb = measured_traffic(dom, n, na, per_launch_slices)
         traffic = int(tb) if tb is not None else None
+        copy_gbs = device_copy_gbs(dev, stream)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "bytes_per_launch": int(bytes_launch), "ms_per_launch": round(per_ms, 5),
-                    "slices_per_launch": per_launch_slices}
+                    "slices_per_launch": per_launch_slices,
+                    "measured_copy_GB_per_s": round(copy_gbs, 1),
+                    "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
 
     mb = model_bytes_per_slice(n, nd, na)
     step_gbs = mb * S / (ms_per_step * 1e-3) / 1e9
