@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def stage_bytes(n: int, nd: int, na: int, tile_entries: int) -> dict:
-    """Algorithmic HBM bytes of one launch (one slice) of each stage.
+    """Algorithmic HBM bytes of each stage for one slice.
 
     Each pass reads and writes its operands once at storage precision, with
     the half-plane grid of G(G/2+1) complex64 values (G = 2N) and H = N_t/2+1
