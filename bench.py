@@ -106,6 +106,18 @@ def model_bytes_per_slice(n: int, nd: int, na: int) -> float:
     return fwd + adj
 
 
+def cpu_model() -> str | None:
+    """The host CPU's model name (first "model name" line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(f64_slice, angles, n_det: int, n_angles_total: int, sample_angles: int) -> dict:
     """FP64 oracle on the host: forward + adjoint of one slice on a subset of angles."""
     import numpy as np
@@ -119,14 +131,19 @@ def cpu_baseline(f64_slice, angles, n_det: int, n_angles_total: int, sample_angl
     ora.radon_adj(s, sub, f64_slice.shape[0])
     dt = time.perf_counter() - t0
     per_slice = dt * n_angles_total / sample_angles
-    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max([p.get("num_threads", 1) for p in blas] or [1])
     return {
         "value": 1.0 / per_slice,
         "unit": "slices/s",
         "cores": int(threads),
         "kind": "oracle",
         "sample": (f"1 slice {f64_slice.shape[0]}^2, forward+adjoint on {sample_angles} of {n_angles_total} "
-                   f"angles in {dt:.1f} s, extrapolated linearly in the angle count"),
+                   f"angles in {dt:.1f} s, extrapolated linearly in the angle count (cost exactly linear in it)"),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
+        "blas": ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in blas})) or None,
+        "blas_threads": int(threads),
     }
 
 
@@ -155,7 +172,7 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
     b = torch.as_tensor(synth.poisson_log_data(b_true, synth.rng_for(4, 1), 1.0e4), dtype=torch.float32,
                         device=dev).contiguous()
     prior = Prior(lam=1.0)
-    L = power_lipschitz(plan, 30) + prior.lipschitz()
+    L_data = power_lipschitz(plan, 30)
     x_ = (torch.arange(n, device=dev, dtype=torch.float32) - n // 2)
     mask = ((x_[None, :] ** 2 + x_[:, None] ** 2) <= (n / 2) ** 2).to(torch.float32)
 
@@ -167,11 +184,11 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
            "iterations": iters, "prior": "qGGMRF p=1.2 sigma=1/0.7 c=1e-4 lambda=1, 26 neighbours",
            "tuning": MBIR_TUNING}
     for name, fn in (("plain", "step"), ("autograd", "step_autograd")):
-        m = MBIR(plan, b, prior, L)
+        m = MBIR(plan, b, prior, L_data=L_data)
         step = getattr(m, fn)
         for _ in range(2):                        # warm-up (iterates restart below)
             step()
-        m = MBIR(plan, b, prior, L)
+        m = MBIR(plan, b, prior, L_data=L_data)
         step = getattr(m, fn)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -185,6 +202,8 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
         out[f"iters_per_s_{name}"] = round(timed / dt, 2)
         out[f"recon_rel_err_{name}"] = round(err(m.x), 5)
         out[f"restarts_{name}"] = m.restarts
+    plan.close()
+    torch.cuda.synchronize()
     return out
 
 
@@ -219,10 +238,10 @@ def paper_shapes_leg(dev, iters: int = 100) -> list:
                             device=dev).contiguous()
         del vol, b_true
         prior = Prior(lam=1.0)
-        L = power_lipschitz(plan, 30) + prior.lipschitz()
-        m = MBIR(plan, b, prior, L)
+        L_data = power_lipschitz(plan, 30)
+        m = MBIR(plan, b, prior, L_data=L_data)
         m.step()
-        m = MBIR(plan, b, prior, L)
+        m = MBIR(plan, b, prior, L_data=L_data)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m.run(iters)
@@ -231,7 +250,9 @@ def paper_shapes_leg(dev, iters: int = 100) -> list:
         out.append({"dataset_shape": name, "slices": nz, "n": n, "n_angles": na, "iterations": iters,
                     "seconds": round(dt, 3), "slice_iters_per_s": round(nz * iters / dt, 1),
                     "paper_seconds": paper_s, "paper_hardware": "4x Tesla P100, 2x Xeon E5-2620 v4"})
+        plan.close()
         del m, plan, b
+        torch.cuda.synchronize()
         torch.cuda.empty_cache()
     return out
 
@@ -247,15 +268,9 @@ def batched_leg(dev, count: int, reps: int) -> dict:
     import synth
     from paper_2304_12934_amd import Plan, SliceGeometry
 
-    rng = synth.rng_for(3, 0)
-    geoms = []
-    for i in range(count):
-        n = int(rng.choice([512, 1024, 2048]))
-        na = int(rng.integers(128, 1501))
-        ang = synth.sparse_angles(rng, na) if i % 2 == 0 else synth.limited_view_angles(rng, na)
-        geoms.append(SliceGeometry(n, n, ang))
+    geoms = [SliceGeometry(n, n, ang) for n, ang in synth.uneven_stack(synth.rng_for(3, 0), count)]
     from paper_2304_12934_amd.autotune import autotune
-    tuning = autotune(geoms, device=dev, reps=2, use_cache=False)
+    tuning = autotune(geoms, device=dev, use_cache=False)
     plan = Plan(geoms, device=dev, tuning=tuning)
     per = Plan(geoms, device=dev, tuning={"batch": 1})
     vol = torch.empty(plan.vol_numel, dtype=torch.float32, device=dev)
@@ -278,6 +293,10 @@ def batched_leg(dev, count: int, reps: int) -> dict:
     t_graph = t(graph.launch)
     t_per = t(lambda: (per.fwd(vol, sino), per.adj(sino, back)))
     info = plan.info()
+    graph.close()
+    plan.close()
+    per.close()
+    torch.cuda.synchronize()
     sizes = {n: sum(1 for g in geoms if g.n == n) for n in (512, 1024, 2048)}
     return {"slices": count, "sizes": sizes, "angles_total": int(sum(len(g.angles) for g in geoms)),
             "batched_graph_slices_per_s": round(count / t_graph, 1),
@@ -325,7 +344,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=2560)
     ap.add_argument("--angles", type=int, default=1024)
     ap.add_argument("--ellipses", type=int, default=20)
-    ap.add_argument("--cpu-angles", type=int, default=4)
+    ap.add_argument("--cpu-angles", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
     ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
@@ -479,6 +498,7 @@ def main() -> int:
         plan_c = Plan.uniform_stack(n, nd, angles, S, center=3.25, device=dev, tuning=tuning or None)
         extensions["fwd_adj_axis_offset_slices_per_s"] = rate(lambda: plan_c.normal(vol, None, sino, back),
                                                                args.steps)
+        plan_c.close()
         del plan_c
         # a host-resident stack three times the device stack (the same slices
         # repeated), streamed through the GPU 8 slices per chunk, against the
@@ -522,9 +542,14 @@ def main() -> int:
             "fwd_slices_per_s": round(fwd_rate, 1), "adj_slices_per_s": round(adj_rate, 1),
             "fwd_pcie_bound_slices_per_s": round(min(h2d * 1e9 / in_b, d2h * 1e9 / out_b), 1),
             "adj_pcie_bound_slices_per_s": round(min(h2d * 1e9 / out_b, d2h * 1e9 / in_b), 1)}
+        torch.cuda.synchronize()
+        plan_s.close()
         del plan_s, h_vol, h_sino, h_back
         print(f"[bench] extensions {extensions}", file=sys.stderr, flush=True)
 
+    # the main stack's plan is closed here, while the runtime is alive
+    torch.cuda.synchronize()
+    plan.close()
     mbir = None
     if not args.no_mbir:
         del vol, sino, back, plan

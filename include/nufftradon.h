@@ -242,42 +242,92 @@ typedef struct {
 nr_status qggmrf_grad(const float* d_vol, int32_t nz, int32_t n, const nr_prior* prior,
                       float scale, float* d_grad_accum, double* d_value, nr_stream stream);
 
-/* One accelerated-gradient iteration with gradient restart (Sec. 3, last
- * paragraph; objective eq. "objfn" with G = 1/2 ||R f - b||^2):
+/* Fills *out with the prior's parameters and neighbour weights (Sec. 3,
+ * eq. "reg3": w_mn over the 26 neighbours, summing to one).  weights:
+ * NR_WEIGHTS_INV_DISTANCE (w proportional to 1/||m - n||, the paper's
+ * "inversely proportional to the distance") or NR_WEIGHTS_GAUSSIAN (w
+ * proportional to exp(-||m - n||^2/2)).  Host only. */
+enum { NR_WEIGHTS_INV_DISTANCE = 0, NR_WEIGHTS_GAUSSIAN = 1 };
+nr_status nr_prior_init(nr_prior* out, float p, float sigma, float c, float lambda, int32_t weights);
+
+/* *out = a Lipschitz constant of grad H (Sec. 3, the prior's part of the
+ * step size): rho'' is largest at 0, rho''(0) = 2/c, so by Gershgorin
+ * L_H = 8 lambda (6 w_face + 12 w_edge + 8 w_corner) / (c sigma^2).  Host only. */
+nr_status nr_prior_lipschitz(const nr_prior* prior, double* out);
+
+/* The largest eigenvalue of R^T R over every slice of the plan, by `iters`
+ * power iterations (v <- R^T R v / ||R^T R v||, norms in float64 on the
+ * device) from a seeded uniform start vector (splitmix64 of seed and the
+ * element index), times `safety` (>= 1): the data term's part of the step
+ * size (Sec. 3).  d_v, d_w: float32 scratch of the plan's volume layout
+ * (max vol_off + N*N, distinct); d_sino: float32 scratch of its sinogram
+ * layout; d_work: one float64.  Device pointers.  Synchronises `stream` and
+ * writes the result to *h_out (host). */
+nr_status nr_power_lipschitz(nr_plan* plan, int32_t iters, uint64_t seed, double safety, float* d_v, float* d_w,
+                             float* d_sino, double* d_work, double* h_out, nr_stream stream);
+
+/* One accelerated-gradient iteration (Sec. 3, last paragraph: an accelerated
+ * gradient method with restart that keeps the objective from rising;
+ * objective eq. "objfn" with G = 1/2 ||R f - b||^2):
  *   g = R^T (R y - b) + grad H(y);  x' = y - inv_L * g (max(x',0) if nonneg)
- *   restart (t = 1) if <g, x' - x> > 0;  t' = (1 + sqrt(1 + 4 t^2))/2
- *   y' = x' + ((t - 1)/t') (x' - x);  x_prev <- x;  x <- x'
+ *   restart (t = 1) if restart and <g, x' - x> > 0
+ *   monotone: reject x' (keep x, t = 1, y = x) if Phi(x') > Phi(x), where
+ *             Phi = 1/2 ||R f - b||^2 + H(f); the first step is accepted
+ *   t' = (1 + sqrt(1 + 4 t^2))/2;  y' = x' + ((t - 1)/t') (x' - x)
+ *   x_prev <- x;  x <- x' (when accepted)
+ * inv_L: step 1/L with L >= the Lipschitz constant of grad Phi (nr_mbir_params);
+ * restart, nonneg, monotone: 0 or 1.  A monotone step evaluates Phi(x') with
+ * one more forward projection and prior pass.
  * All slices of the plan must share one N and the volume is the plan's
- * slices stacked in order (prior couples consecutive slices).  d_b: data,
- * same layout as radon_fwd's output.  d_x, d_x_prev, d_y, d_grad: float32
- * volumes (d_grad holds g on return).  The prior uses the plan's slices as
- * consecutive z planes: slice z must sit at vol_off = z*N*N.  d_state: 8
- * float64 on the device, {t, last <g, x'-x>, nonfinite flag, restart count,
- * beta, 3 reserved}; set t = 1 and the rest 0 before the first step.
- * d_scratch: float32 scratch of the plan's sinogram size (max sino_off +
- * n_angles*N_t).  Everything stays on the device: no host synchronisation;
- * read d_state when needed (flag != 0 means a NaN/Inf appeared). */
+ * slices stacked in order (prior couples consecutive slices): slice z must
+ * sit at vol_off = z*N*N.  d_b: data, same layout as radon_fwd's output.
+ * d_x, d_x_prev, d_y, d_grad: float32 volumes (d_grad holds g on return;
+ * d_x_prev holds the previous x, or x itself after a rejected step).
+ * d_state: NR_MBIR_STATE_DOUBLES float64 on the device, set by
+ * mbir_state_init before the first step: {t, last <g, x'-x>, nonfinite
+ * flag, restart count, beta, Phi(x), Phi(x) known, data term of x', prior
+ * of x', last x' accepted, rejected steps, 5 reserved}.  d_scratch: float32
+ * scratch of the plan's sinogram size (max sino_off + n_angles*N_t).
+ * Everything stays on the device: no host synchronisation; read d_state
+ * when needed (flag != 0 means a NaN/Inf appeared). */
 typedef struct {
   float inv_L;
+  int32_t restart;
   int32_t nonneg;
+  int32_t monotone;
 } nr_mbir;
+
+#define NR_MBIR_STATE_DOUBLES 16
 
 nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
                     const float* d_b, float* d_x, float* d_x_prev, float* d_y, float* d_grad,
                     float* d_scratch, double* d_state, nr_stream stream);
 
+/* Resets an MBIR state (NR_MBIR_STATE_DOUBLES float64 on the device): t = 1,
+ * every other entry 0.  Asynchronous on `stream`. */
+nr_status mbir_state_init(double* d_state, nr_stream stream);
+
+/* The step parameters of mbir_step: inv_L = 1/(lipschitz_data + L_H(prior))
+ * with lipschitz_data the largest eigenvalue of R^T R (nr_power_lipschitz)
+ * and L_H from nr_prior_lipschitz (prior may be NULL: no prior); restart,
+ * nonneg and monotone copied (0 or 1).  Host only. */
+nr_status nr_mbir_params(double lipschitz_data, const nr_prior* prior, int32_t restart, int32_t nonneg,
+                         int32_t monotone, nr_mbir* out);
+
 /* The update half of mbir_step for a gradient computed elsewhere (e.g. by
  * autograd through radon_fwd / radon_adj / qggmrf_grad): given g = grad
  * Phi(y) in d_grad, performs the restart test, the momentum update and
  * x_prev <- x, x <- x', y <- y' over `count` float32 elements, with d_state
- * as for mbir_step.  Device pointers; no host synchronisation. */
+ * as for mbir_step.  Device pointers; no host synchronisation.  The
+ * monotone step needs the objective and is refused here (NR_INVALID_ARG). */
 nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
                       int64_t count, double* d_state, nr_stream stream);
 
 /* Graphs: a whole forward/adjoint pass or a run of MBIR steps captured once
  * (on a private stream) into a HIP graph and replayed with one launch.  The
  * buffers are bound at capture; the plan must outlive the graph and stay
- * bound.  what: 1 = radon_fwd(d_vol_in -> d_sino), 2 = radon_adj(d_sino ->
+ * bound: nr_graph_launch refuses (NR_INVALID_ARG) a graph whose plan has
+ * been re-tuned or re-bound since the capture.  what: 1 = radon_fwd(d_vol_in -> d_sino), 2 = radon_adj(d_sino ->
  * d_vol_out), 3 = both in that order. */
 typedef struct nr_graph nr_graph;
 nr_status nr_graph_capture_radon(nr_plan* plan, int32_t what, const float* d_vol_in, float* d_sino,
@@ -287,6 +337,31 @@ nr_status nr_graph_capture_mbir(nr_plan* plan, const nr_prior* prior, const nr_m
                                 double* d_state, int32_t iters, nr_graph** out);
 nr_status nr_graph_launch(nr_graph* graph, nr_stream stream);
 nr_status nr_graph_destroy(nr_graph* graph);
+
+/* Autotuner (Sec. 4: the execution schedule of the C++ core; batching and
+ * the spreading tile are this library's own parameters).  Times forward +
+ * adjoint passes (radon_normal, three repetitions after a warm-up, HIP
+ * events on `stream`) of the plan's stack under candidate settings of the
+ * tuning keys "batch_mb" {1, 160, 640, 1400, 2048}, "streams" {1, 2, 3, 6},
+ * the spreading tile "tile_w" x "tile_h" {64x32, 32x32, 64x64, 128x32} and
+ * "chunk" {256, 512, 1024}, one key at a time from the plan's current
+ * setting (coordinate search), and keeps the fastest.  Every candidate
+ * computes the same operator (the spreading sums differ in float32 order).
+ * d_scratch (256-byte aligned, `bytes` long, device) holds the passes'
+ * buffers and each candidate's workspace; candidates that do not fit are
+ * skipped (nr_autotune_scratch_bytes gives a size that fits them all).
+ * cache_json (may be NULL): a JSON file of tunings keyed by geometry and
+ * device; a hit applies the cached setting without timing, a miss is
+ * written back.  On return the plan holds the chosen setting and is
+ * unbound: query nr_plan_workspace_bytes and call nr_plan_bind.
+ * Synchronises `stream`. */
+nr_status nr_autotune(nr_plan* plan, void* d_scratch, size_t bytes, const char* cache_json, nr_stream stream);
+nr_status nr_autotune_scratch_bytes(nr_plan* plan, size_t* bytes);
+
+/* Current value of a tuning key of nr_plan_tune, or "autotune_us" (best pass
+ * time of the last nr_autotune in microseconds, -1 if none or cached) and
+ * "autotune_trials" (candidates it timed). */
+nr_status nr_plan_get_tune(const nr_plan* plan, const char* key, int64_t* value);
 
 /* Host-only helpers (no device needed), used to test the plan's tables.
  * nr_kb_eval: for the plan-independent kernel with (width, beta), evaluates

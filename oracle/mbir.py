@@ -5,14 +5,16 @@ Sec. 3, eq. "objfn": ``f = argmin G(f) + H(f)`` with the data term
 ``grad G = R*(R f - b)``; that is literally true for ``G = 1/2 ||R f - b||^2``,
 which is the reading used here, with ``R*`` the exact transpose.
 
-The paper's optimiser is "a monotonic accelerated gradient method with
-restart" (Sec. 3, last paragraph) without further detail.  The loop below
-is the Nesterov/FISTA form with the gradient restart test and a fixed
-``1/L`` step; its agreement with tomoCAM's own optimiser is parity
-unpinned (no code or iterates are published).  ``L = L_R + L_H`` where
-``L_R`` is the largest eigenvalue of ``R^T R`` (power iteration) and
-``L_H = 8 lambda/(c sigma^2)`` bounds the prior Hessian (``max rho'' = 2/c``
-at zero, weights summing to one, Gershgorin).
+Sec. 3 (last paragraph) names its optimiser only as an accelerated
+gradient method with restart whose objective does not increase, citing
+Giselsson and Boyd.  The loop below is the Nesterov/FISTA form with a fixed
+``1/L`` step, the gradient restart test (``restart``) and, when
+``monotone``, a rejection test that keeps ``x`` (and restarts the momentum)
+whenever a step would raise the objective; its agreement with tomoCAM's own
+optimiser is parity unpinned (no code or iterates are published).
+``L = L_R + L_H`` where ``L_R`` is the largest eigenvalue of ``R^T R``
+(power iteration) and ``L_H = 8 lambda/(c sigma^2)`` bounds the prior
+Hessian (``max rho'' = 2/c`` at zero, weights summing to one, Gershgorin).
 """
 
 from __future__ import annotations
@@ -89,38 +91,58 @@ class State:
     t: float = 1.0
     k: int = 0
     restarts: int = 0
+    phi: float | None = None     # objective at x, once a monotone step has evaluated it
+    rejected: int = 0            # steps the monotone test rejected
 
 
-def step(state: State, b, A, At, prior: Prior | None, L: float, nonneg: bool = False) -> State:
-    """One accelerated-gradient iteration with gradient restart.
+def step(state: State, b, A, At, prior: Prior | None, L: float, nonneg: bool = False,
+         restart: bool = True, monotone: bool = False) -> State:
+    """One accelerated-gradient iteration.
 
-    ``g = grad Phi(y_k)``; ``x_{k+1} = y_k - g/L`` (projected onto ``x >= 0``
-    when ``nonneg``); if ``<g, x_{k+1} - x_k> > 0`` the momentum restarts
-    (``t_k = 1``); ``t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2`` and
-    ``y_{k+1} = x_{k+1} + ((t_k - 1)/t_{k+1}) (x_{k+1} - x_k)``.
+    ``g = grad Phi(y_k)``; the candidate ``z = y_k - g/L`` (projected onto
+    ``x >= 0`` when ``nonneg``).  With ``restart``, ``<g, z - x_k> > 0``
+    resets the momentum (``t_k = 1``).  With ``monotone``, ``z`` is rejected
+    when ``Phi(z) > Phi(x_k)``: ``x_{k+1} = x_k``, ``t_k = 1`` and
+    ``y_{k+1} = x_{k+1}``; the first step, before any ``Phi(x)`` is known, is
+    accepted.  Otherwise ``x_{k+1} = z``.  Then ``t_{k+1} = (1 + sqrt(1 + 4
+    t_k^2))/2`` and ``y_{k+1} = x_{k+1} + ((t_k - 1)/t_{k+1}) (x_{k+1} - x_k)``.
     """
     g = gradient(state.y, b, A, At, prior)
-    x_new = state.y - g / L
+    z = state.y - g / L
     if nonneg:
-        x_new = np.maximum(x_new, 0.0)
+        z = np.maximum(z, 0.0)
     t = state.t
-    restarts = state.restarts
-    if float(np.sum(g * (x_new - state.x))) > 0.0:
+    restarts, rejected, phi = state.restarts, state.rejected, state.phi
+    if restart and float(np.sum(g * (z - state.x))) > 0.0:
         t = 1.0
         restarts += 1
+    accept = True
+    if monotone:
+        phi_z = objective(z, b, A, prior)
+        if phi is not None and not phi_z <= phi:
+            accept = False
+            t = 1.0
+            rejected += 1
+        else:
+            phi = phi_z
     t_new = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * t * t))
-    y_new = x_new + ((t - 1.0) / t_new) * (x_new - state.x)
-    return State(x_new, y_new, t_new, state.k + 1, restarts)
+    if accept:
+        x_new = z
+        y_new = x_new + ((t - 1.0) / t_new) * (x_new - state.x)
+    else:
+        x_new = state.x
+        y_new = state.x.copy()
+    return State(x_new, y_new, t_new, state.k + 1, restarts, phi, rejected)
 
 
 def run(b, A, At, shape, prior: Prior | None, L: float, iters: int,
         x0: np.ndarray | None = None, nonneg: bool = False,
-        callback: Callable | None = None) -> State:
+        callback: Callable | None = None, restart: bool = True, monotone: bool = False) -> State:
     """``iters`` iterations from ``x_0`` (zero by default), ``y_0 = x_0``, ``t_0 = 1``."""
     x0 = np.zeros(shape) if x0 is None else np.asarray(x0, dtype=np.float64)
     st = State(x0.copy(), x0.copy())
     for _ in range(iters):
-        st = step(st, b, A, At, prior, L, nonneg)
+        st = step(st, b, A, At, prior, L, nonneg, restart, monotone)
         if callback is not None:
             callback(st)
     return st

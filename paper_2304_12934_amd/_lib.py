@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnufftradon.so")
 
@@ -48,7 +48,12 @@ class NrPrior(ctypes.Structure):
 
 
 class NrMbir(ctypes.Structure):
-    _fields_ = [("inv_L", c_float), ("nonneg", c_int32)]
+    _fields_ = [("inv_L", c_float), ("restart", c_int32), ("nonneg", c_int32), ("monotone", c_int32)]
+
+
+NR_MBIR_STATE_DOUBLES = 16
+NR_WEIGHTS_INV_DISTANCE = 0
+NR_WEIGHTS_GAUSSIAN = 1
 
 
 class NrError(RuntimeError):
@@ -83,6 +88,15 @@ SIGNATURES = {
                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mbir_update": (c_int32, [POINTER(NrMbir), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                               c_void_p]),
+    "mbir_state_init": (c_int32, [c_void_p, c_void_p]),
+    "nr_prior_init": (c_int32, [POINTER(NrPrior), c_float, c_float, c_float, c_float, c_int32]),
+    "nr_prior_lipschitz": (c_int32, [POINTER(NrPrior), POINTER(c_double)]),
+    "nr_mbir_params": (c_int32, [c_double, POINTER(NrPrior), c_int32, c_int32, c_int32, POINTER(NrMbir)]),
+    "nr_power_lipschitz": (c_int32, [c_void_p, c_int32, c_uint64, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     POINTER(c_double), c_void_p]),
+    "nr_autotune": (c_int32, [c_void_p, c_void_p, c_size_t, c_char_p, c_void_p]),
+    "nr_autotune_scratch_bytes": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nr_plan_get_tune": (c_int32, [c_void_p, c_char_p, POINTER(c_int64)]),
     "nr_graph_capture_radon": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_void_p)]),
     "nr_graph_capture_mbir": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_void_p)]),

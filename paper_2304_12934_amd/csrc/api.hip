@@ -2,8 +2,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,9 +32,17 @@ struct StageEvents {
   hipEvent_t start, stop;
 };
 
+// Every plan state that kernel arguments depend on (a layout, a bound
+// workspace) gets a fresh generation number, unique across plans.
+static std::atomic<uint64_t> g_generation{1};
+static uint64_t next_generation() { return g_generation.fetch_add(1); }
+
 struct nr_plan {
   nr::Plan p;
+  uint64_t gen = next_generation();   // changes on every re-layout and re-bind
   bool profiling = false;
+  double tune_best_ms = -1.0;            // last nr_autotune: best pass time
+  int tune_trials = 0;
   std::vector<StageEvents> recorded;
   std::vector<hipEvent_t> pool;
   std::vector<SliceDesc> host_descs;
@@ -77,6 +92,8 @@ struct nr_plan {
 struct nr_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const nr_plan* plan = nullptr;   // the captured plan and its generation at capture
+  uint64_t gen = 0;
   ~nr_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -189,11 +206,12 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
 // forward on its lane, with no join in between.
 nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const float* vol_in, float* vol_out,
                       const float* sino_in, float* sino_out, hipStream_t st, const char* where,
-                      const nr_fbp* fbp = nullptr) {
+                      const nr_fbp* fbp = nullptr, const void* ws = nullptr) {
   const nr::Plan& p = plan->p;
   // while stages are being timed they run one at a time on st, so that each
-  // event pair times its stage alone
-  const int nl = plan->profiling ? 1 : p.n_lanes;
+  // event pair times its stage alone; a workspace other than the bound one
+  // (the static one) is used from st alone too
+  const int nl = (plan->profiling || ws) ? 1 : p.n_lanes;
   if (nl > 1) {
     hipError_t e = ensure_lanes(plan, nl);
     if (e == hipSuccess) e = hipEventRecord(plan->fork, st);
@@ -202,7 +220,7 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
   }
   auto lane_stream = [&](const nr::Batch& bt) { return nl > 1 ? plan->lanes[size_t(bt.lane)] : st; };
   const nrk::KBArgs kb = kb_args(p);
-  const char* base = static_cast<const char*>(p.d_ws);
+  const char* base = static_cast<const char*>(ws ? ws : p.d_ws);
   nrk::LaunchArgs a{};
   a.descs = reinterpret_cast<const SliceDesc*>(base + p.off_desc);
   a.halo = p.halo;
@@ -220,7 +238,6 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
     std::vector<const nr::StageLaunch*> seq;
     if (fwd)
       for (const nr::StageLaunch& sl : bt.fwd) seq.push_back(&sl);
-    if (fwd && b) seq.push_back(nullptr);   // the residual of the batch's slices
     if (adj)
       for (const nr::StageLaunch& sl : bt.adj) seq.push_back(&sl);
     // Lanes start skewed: lane l's first batch waits until lane l-1's first
@@ -237,18 +254,7 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
         const hipError_t e = hipEventRecord(plan->lane_skew[size_t(bt.lane)], bs);
         if (e != hipSuccess) return hip_fail(e, where);
       }
-      const nr::StageLaunch* slp = seq[si];
-      if (!slp) {
-        hipError_t e = hipSuccess;
-        for (int s : bt.slices) {
-          const nr_slice& sl = p.slices[size_t(s)];
-          const size_t off = size_t(sl.sino_off), cnt = size_t(sl.n_angles) * sl.n_det;
-          e = timed(plan, kStageResidual, bs, [&] { return nrk::launch_residual(sino_out + off, b + off, cnt, bs); });
-          if (e != hipSuccess) return hip_fail(e, where);
-        }
-        continue;
-      }
-      const nr::StageLaunch& sl = *slp;
+      const nr::StageLaunch& sl = *seq[si];
       const bool spread = sl.stage == nr::Stage::Spread || sl.stage == nr::Stage::SpreadZero;
       hipError_t e = hipSuccess;
       if (spread && p.tune.spread_mode == 1) {
@@ -265,6 +271,8 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
         nrk::LaunchArgs la = a;
         la.work = reinterpret_cast<const WorkItem*>(base + p.off_work + sl.work_off);
         la.n_work = sl.n_work;
+        // the stage that writes the sinogram rows subtracts b as it stores them
+        if (sl.stage == nr::Stage::FwdRadial || (sl.stage == nr::Stage::FwdInterp && sl.L > 0)) la.sino_sub = b;
         e = timed(plan, stage_event_id(sl.stage), bs, [&] {
           return nrk::launch_stage(static_cast<nrk::StageKind>(int(sl.stage)), sl.L, la, kb, p.kb.W,
                                    p.tune.tile_w, p.tune.tile_h, bs);
@@ -319,6 +327,14 @@ nr_status check_prior(const nr_prior* prior) {
   return NR_OK;
 }
 
+nr_status check_mbir(const nr_mbir* m) {
+  if (!(m->inv_L > 0.0f) || !std::isfinite(m->inv_L)) return fail(NR_INVALID_ARG, "inv_L must be finite and > 0");
+  if ((m->restart != 0 && m->restart != 1) || (m->nonneg != 0 && m->nonneg != 1) ||
+      (m->monotone != 0 && m->monotone != 1))
+    return fail(NR_INVALID_ARG, "restart, nonneg and monotone must be 0 or 1");
+  return NR_OK;
+}
+
 nrk::PriorArgs prior_args(const nr_prior* p) {
   return nrk::PriorArgs{p->p, p->sigma, p->c, p->lambda, p->w_face, p->w_edge, p->w_corner};
 }
@@ -358,7 +374,186 @@ nr_status capture(nr_plan* plan, nr_graph** out, F&& enqueue) {
     delete g;
     return status;
   }
+  g->plan = plan;
+  g->gen = plan->gen;
   *out = g;
+  return NR_OK;
+}
+
+// Copies the plan's tables, the slice descriptors `descs` (pointing into the
+// workspace at base) and the work lists into that workspace on st.  The host
+// sources must stay alive until the copies have run.
+hipError_t upload_tables(const nr::Plan& p, char* base, const std::vector<SliceDesc>& descs, hipStream_t st) {
+  auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+  for (auto& kv : p.deapod)
+    if ((e = up(p.off_deapod.at(kv.first), kv.second.data(), kv.second.size() * sizeof(float)))) return e;
+  for (auto& kv : p.twiddle)
+    if ((e = up(p.off_twiddle.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) return e;
+  for (auto& kv : p.shift)
+    if ((e = up(p.off_shift.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) return e;
+  for (const nr::Geom& g : p.geoms) {
+    if ((e = up(g.off_gxy, g.gxy.data(), g.gxy.size() * sizeof(double)))) return e;
+    if ((e = up(g.off_flip, g.flip.data(), g.flip.size() * sizeof(int32_t)))) return e;
+    if ((e = up(g.off_pts, g.pts.data(), g.pts.size() * sizeof(int32_t)))) return e;
+    if ((e = up(g.off_items, g.items.data(), g.items.size() * sizeof(SpreadItem)))) return e;
+    if ((e = up(g.off_zero, g.zero_tiles.data(), g.zero_tiles.size() * sizeof(int32_t)))) return e;
+    if ((e = up(g.off_ipts, g.ipts.data(), g.ipts.size() * sizeof(int32_t)))) return e;
+    if ((e = up(g.off_iitems, g.iitems.data(), g.iitems.size() * sizeof(SpreadItem)))) return e;
+  }
+  if ((e = up(p.off_desc, descs.data(), descs.size() * sizeof(SliceDesc)))) return e;
+  return up(p.off_work, p.work.data(), p.work.size() * sizeof(WorkItem));
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner cache: a JSON object of objects, {"<key>": {"tile_w": 64, ...}}
+// ---------------------------------------------------------------------------
+
+using CacheEntry = std::vector<std::pair<std::string, double>>;
+using Cache = std::vector<std::pair<std::string, CacheEntry>>;
+
+struct JsonIn {
+  const std::string& t;
+  size_t i = 0;
+  void ws() {
+    while (i < t.size() && std::isspace(static_cast<unsigned char>(t[i]))) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string& out) {
+    if (!eat('"')) return false;
+    out.clear();
+    while (i < t.size() && t[i] != '"') {
+      if (t[i] == '\\' && i + 1 < t.size()) ++i;
+      out.push_back(t[i++]);
+    }
+    return eat('"');
+  }
+  bool num(double& v) {
+    ws();
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    v = std::strtod(b, &e);
+    if (e == b) return false;
+    i += size_t(e - b);
+    return true;
+  }
+};
+
+// Parses the cache file's text; false (and an empty cache) when it is not of that form.
+bool parse_cache(const std::string& text, Cache& out) {
+  out.clear();
+  JsonIn in{text};
+  if (!in.eat('{')) return false;
+  if (in.eat('}')) return true;
+  do {
+    std::string key;
+    CacheEntry e;
+    if (!in.str(key) || !in.eat(':') || !in.eat('{')) return out.clear(), false;
+    if (!in.eat('}')) {
+      do {
+        std::string name;
+        double v = 0.0;
+        if (!in.str(name) || !in.eat(':') || !in.num(v)) return out.clear(), false;
+        e.emplace_back(name, v);
+      } while (in.eat(','));
+      if (!in.eat('}')) return out.clear(), false;
+    }
+    out.emplace_back(key, e);
+  } while (in.eat(','));
+  return in.eat('}') || (out.clear(), false);
+}
+
+std::string format_cache(const Cache& c) {
+  std::string s = "{\n";
+  for (size_t k = 0; k < c.size(); ++k) {
+    s += " \"" + c[k].first + "\": {";
+    for (size_t j = 0; j < c[k].second.size(); ++j) {
+      char buf[64];
+      std::snprintf(buf, sizeof(buf), "%.17g", c[k].second[j].second);
+      s += (j ? ", \"" : "\"") + c[k].second[j].first + "\": " + buf;
+    }
+    s += k + 1 < c.size() ? "},\n" : "}\n";
+  }
+  return s + "}\n";
+}
+
+// FNV-1a over the bytes of the plan's geometry and kernel parameters and the
+// device's name: the cache key of a tuning.
+std::string geometry_key(const nr::Plan& p, const std::string& device) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* data, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 1099511628211ull;
+  };
+  mix(device.data(), device.size());
+  mix(&p.kb.W, sizeof(p.kb.W));
+  mix(&p.kb.beta, sizeof(p.kb.beta));
+  for (const nr_slice& sl : p.slices) {
+    const int32_t v[3] = {sl.n, sl.n_det, sl.n_angles};
+    mix(v, sizeof(v));
+    mix(&sl.center, sizeof(sl.center));
+    mix(p.angles.data() + sl.angle_off, size_t(sl.n_angles) * sizeof(double));
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", static_cast<unsigned long long>(h));
+  return buf;
+}
+
+const char* const kTuneKeys[] = {"tile_w", "tile_h", "chunk", "batch_mb", "streams"};
+
+int64_t tune_value(const nr::Tuning& t, const std::string& k) {
+  if (k == "tile_w") return t.tile_w;
+  if (k == "tile_h") return t.tile_h;
+  if (k == "chunk") return t.chunk;
+  if (k == "batch_mb") return t.batch_mb;
+  if (k == "streams") return t.streams;
+  if (k == "batch") return t.batch;
+  if (k == "interp_mode") return t.interp_mode;
+  if (k == "spread_mode") return t.spread_mode;
+  return INT64_MIN;
+}
+
+void set_tune_value(nr::Tuning& t, const std::string& k, int64_t v) {
+  if (k == "tile_w") t.tile_w = int(v);
+  else if (k == "tile_h") t.tile_h = int(v);
+  else if (k == "chunk") t.chunk = int(v);
+  else if (k == "batch_mb") t.batch_mb = int(v);
+  else if (k == "streams") t.streams = int(v);
+}
+
+// The autotuner's search space: the batch budget, the number of streams,
+// the spreading tile and the spreading/interpolation item size.
+const int kTuneBudgets[] = {1, 160, 640, 1400, 2048};
+const int kTuneStreams[] = {1, 2, 3, 6};
+const int kTuneTiles[][2] = {{64, 32}, {32, 32}, {64, 64}, {128, 32}};
+const int kTuneChunks[] = {256, 512, 1024};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Buffers of one timed pass in the autotuner's scratch: volume, back-projection, sinogram.
+size_t tune_buffer_bytes(const nr::Plan& p) {
+  return 2 * align256(vol_extent(p) * sizeof(float)) + align256(sino_extent(p) * sizeof(float));
+}
+
+// Workspace bytes of the plan under tuning t (lays the plan out for it).
+nr_status layout_bytes(nr_plan* plan, const nr::Tuning& t, size_t& bytes) {
+  plan->p.tune = t;
+  plan->p.laid_out = false;
+  std::string err;
+  const nr_status st = nr::layout_plan(plan->p, err);
+  if (st != NR_OK) return fail(st, err);
+  bytes = plan->p.ws_bytes;
   return NR_OK;
 }
 
@@ -422,37 +617,15 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
                                             std::to_string(p.ws_bytes));
   if (nr_status st = pending_error("before nr_plan_bind")) return st;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(d_ws);
-  plan->host_descs = nr::slice_descs(p, base);
-  auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
-    if (n == 0) return hipSuccess;
-    return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, st);
-  };
-  hipError_t e = hipSuccess;
-  for (auto& kv : p.deapod)
-    if ((e = up(p.off_deapod.at(kv.first), kv.second.data(), kv.second.size() * sizeof(float)))) break;
-  for (auto& kv : p.twiddle)
-    if (!e && (e = up(p.off_twiddle.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) break;
-  for (auto& kv : p.shift)
-    if (!e && (e = up(p.off_shift.at(kv.first), kv.second.data(), kv.second.size() * sizeof(nr::f2)))) break;
-  for (nr::Geom& g : p.geoms) {
-    if (e) break;
-    if ((e = up(g.off_gxy, g.gxy.data(), g.gxy.size() * sizeof(double)))) break;
-    if ((e = up(g.off_flip, g.flip.data(), g.flip.size() * sizeof(int32_t)))) break;
-    if ((e = up(g.off_pts, g.pts.data(), g.pts.size() * sizeof(int32_t)))) break;
-    if ((e = up(g.off_items, g.items.data(), g.items.size() * sizeof(SpreadItem)))) break;
-    if ((e = up(g.off_zero, g.zero_tiles.data(), g.zero_tiles.size() * sizeof(int32_t)))) break;
-    if ((e = up(g.off_ipts, g.ipts.data(), g.ipts.size() * sizeof(int32_t)))) break;
-    if ((e = up(g.off_iitems, g.iitems.data(), g.iitems.size() * sizeof(SpreadItem)))) break;
-  }
-  if (!e) e = up(p.off_desc, plan->host_descs.data(), plan->host_descs.size() * sizeof(SliceDesc));
-  if (!e) e = up(p.off_work, p.work.data(), p.work.size() * sizeof(WorkItem));
+  plan->host_descs = nr::slice_descs(p, static_cast<char*>(d_ws));
+  hipError_t e = upload_tables(p, static_cast<char*>(d_ws), plan->host_descs, st);
   // the host tables are read by the copies: wait here so the caller may reuse
   // or destroy the plan freely afterwards
   if (!e) e = hipStreamSynchronize(st);
   if (e) return hip_fail(e, "nr_plan_bind upload");
   p.d_ws = d_ws;
   p.d_ws_bytes = bytes;
+  plan->gen = next_generation();
   return NR_OK;
 }
 
@@ -494,6 +667,7 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
   plan->p.laid_out = false;
   plan->p.d_ws = nullptr;
   plan->p.d_ws_bytes = 0;
+  plan->gen = next_generation();
   return NR_OK;
 }
 
@@ -633,14 +807,18 @@ nr_status radon_residual(nr_plan* plan, const float* d_vol, const float* d_b, fl
                          nr_stream stream) {
   if (nr_status st = check_bound(plan)) return st;
   if (!d_vol || !d_b || !d_r) return fail(NR_INVALID_ARG, "radon_residual: NULL argument");
-  const size_t sino_total = sino_extent(plan->p);
-  if (nr_status s = radon_fwd(plan, d_vol, d_r, stream)) return s;
+  if (nr_status st = pending_error("before radon_residual")) return st;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const hipError_t e = timed(plan, kStageResidual, st, [&] {
-    return d_value ? nrk::launch_residual_norm(d_r, d_b, sino_total, d_value, st)
-                   : nrk::launch_residual(d_r, d_b, sino_total, st);
-  });
-  if (e != hipSuccess) return hip_fail(e, "radon_residual launch");
+  // the forward's radial stage stores R f - b
+  if (nr_status s = run_batches(plan, true, d_b, false, d_vol, nullptr, nullptr, d_r, st, "radon_residual launch"))
+    return s;
+  if (d_value) {
+    const size_t sino_total = sino_extent(plan->p);
+    const hipError_t e = timed(plan, kStageResidual, st, [&] {
+      return nrk::launch_half_sum_squares(d_r, sino_total, d_value, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "radon_residual norm");
+  }
   return NR_OK;
 }
 
@@ -663,7 +841,7 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   if (!params || !d_b || !d_x || !d_x_prev || !d_y || !d_grad || !d_scratch || !d_state)
     return fail(NR_INVALID_ARG, "mbir_step: NULL argument");
   if (nr_status st = check_prior(prior)) return st;
-  if (!(params->inv_L > 0.0f)) return fail(NR_INVALID_ARG, "inv_L must be > 0");
+  if (nr_status st = check_mbir(params)) return st;
   const nr::Plan& p = plan->p;
   const int n = p.slices[0].n;
   const int nz = int(p.slices.size());
@@ -673,19 +851,40 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
       return fail(NR_INVALID_ARG, "mbir_step: slices must share N and sit at vol_off = z*N*N");
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t count = size_t(nz) * n * n;
+  const nrk::PriorArgs pa = prior_args(prior);
   // R^T (R y - b) into d_grad, batch by batch
   if (nr_status s = radon_normal(plan, d_y, d_b, d_scratch, d_grad, stream)) return s;
   hipError_t e = hipSuccess;
   if (prior->lambda > 0.0f) {
-    const nrk::PriorArgs pa = prior_args(prior);
     e = timed(plan, kStagePrior, st, [&] { return nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, pa, 1.0f, st); });
     if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
   }
+  if (!params->monotone) {
+    e = timed(plan, kStageUpdate, st, [&] {
+      return nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, count, params->inv_L, params->nonneg,
+                                     params->restart, d_state, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "mbir_step update");
+    return NR_OK;
+  }
+  // monotone: the candidate x' (into d_x_prev) and its objective
   e = timed(plan, kStageUpdate, st, [&] {
-    return nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(nz) * n * n, params->inv_L, params->nonneg,
-                                   d_state, st);
+    return nrk::launch_mbir_candidate(d_x, d_x_prev, d_y, d_grad, count, params->inv_L, params->nonneg, d_state,
+                                      st);
   });
-  if (e != hipSuccess) return hip_fail(e, "mbir_step update");
+  if (e != hipSuccess) return hip_fail(e, "mbir_step candidate");
+  if (nr_status s = radon_residual(plan, d_x_prev, d_b, d_scratch, d_state + nrk::kStPhiData, stream)) return s;
+  e = timed(plan, kStagePrior, st, [&] {
+    return prior->lambda > 0.0f
+               ? nrk::launch_qggmrf(d_x_prev, nullptr, d_state + nrk::kStPhiPrior, nz, n, pa, 1.0f, st)
+               : nrk::launch_set_double(d_state + nrk::kStPhiPrior, 0.0, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "mbir_step candidate prior");
+  e = timed(plan, kStageUpdate, st, [&] {
+    return nrk::launch_mbir_finish_monotone(d_x, d_x_prev, d_y, count, params->restart, d_state, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "mbir_step monotone update");
   return NR_OK;
 }
 
@@ -694,11 +893,22 @@ nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float*
   if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state)
     return fail(NR_INVALID_ARG, "mbir_update: NULL argument");
   if (count < 1) return fail(NR_INVALID_ARG, "mbir_update: count must be >= 1");
-  if (!(params->inv_L > 0.0f)) return fail(NR_INVALID_ARG, "inv_L must be > 0");
+  if (nr_status st = check_mbir(params)) return st;
+  if (params->monotone)
+    return fail(NR_INVALID_ARG, "mbir_update: the monotone step needs the objective (use mbir_step)");
   if (nr_status st = pending_error("before mbir_update")) return st;
   const hipError_t e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(count), params->inv_L,
-                                               params->nonneg, d_state, static_cast<hipStream_t>(stream));
+                                               params->nonneg, params->restart, d_state,
+                                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mbir_update launch");
+  return NR_OK;
+}
+
+nr_status mbir_state_init(double* d_state, nr_stream stream) {
+  if (!d_state) return fail(NR_INVALID_ARG, "mbir_state_init: NULL state");
+  if (nr_status st = pending_error("before mbir_state_init")) return st;
+  const hipError_t e = nrk::launch_mbir_state_init(d_state, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mbir_state_init launch");
   return NR_OK;
 }
 
@@ -733,6 +943,9 @@ nr_status nr_graph_capture_mbir(nr_plan* plan, const nr_prior* prior, const nr_m
 
 nr_status nr_graph_launch(nr_graph* graph, nr_stream stream) {
   if (!graph || !graph->exec) return fail(NR_INVALID_ARG, "graph is NULL");
+  // the kernels' arguments hold the workspace and layout of the capture
+  if (graph->plan && graph->plan->gen != graph->gen)
+    return fail(NR_INVALID_ARG, "nr_graph_launch: the plan was re-tuned or re-bound since the capture");
   if (nr_status st = pending_error("before nr_graph_launch")) return st;
   const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -753,6 +966,272 @@ nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u,
     if (u && phi) phi[i] = kb.phi(u[i]);
     if (u && phi_poly) phi_poly[i] = kb.phi_poly(u[i]);
     if (xi && phihat) phihat[i] = kb.phihat(xi[i]);
+  }
+  return NR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// set-up arithmetic of the MBIR step (Sec. 3)
+// ---------------------------------------------------------------------------
+
+nr_status nr_prior_init(nr_prior* out, float p, float sigma, float c, float lambda, int32_t weights) {
+  if (!out) return fail(NR_INVALID_ARG, "nr_prior_init: out is NULL");
+  double w[4] = {0.0, 0.0, 0.0, 0.0};   // by squared distance 1, 2, 3
+  for (int d2 = 1; d2 <= 3; ++d2) {
+    if (weights == NR_WEIGHTS_INV_DISTANCE) w[d2] = 1.0 / std::sqrt(double(d2));
+    else if (weights == NR_WEIGHTS_GAUSSIAN) w[d2] = std::exp(-0.5 * d2);
+    else return fail(NR_INVALID_ARG, "nr_prior_init: weights must be NR_WEIGHTS_INV_DISTANCE or NR_WEIGHTS_GAUSSIAN");
+  }
+  const double total = 6.0 * w[1] + 12.0 * w[2] + 8.0 * w[3];   // 6 faces, 12 edges, 8 corners
+  *out = nr_prior{p, sigma, c, lambda, float(w[1] / total), float(w[2] / total), float(w[3] / total)};
+  return check_prior(out);
+}
+
+nr_status nr_prior_lipschitz(const nr_prior* prior, double* out) {
+  if (!out) return fail(NR_INVALID_ARG, "nr_prior_lipschitz: out is NULL");
+  if (nr_status st = check_prior(prior)) return st;
+  // Hessian row m of H: diagonal (2 lambda/sigma^2) sum_n w_mn rho''(.), off-diagonal
+  // -(2 lambda/sigma^2) w_mn rho''(.), with 0 <= rho'' <= rho''(0) = 2/c (Gershgorin)
+  const double wsum = 6.0 * prior->w_face + 12.0 * prior->w_edge + 8.0 * prior->w_corner;
+  *out = 8.0 * double(prior->lambda) * wsum / (double(prior->c) * double(prior->sigma) * double(prior->sigma));
+  return NR_OK;
+}
+
+nr_status nr_mbir_params(double lipschitz_data, const nr_prior* prior, int32_t restart, int32_t nonneg,
+                         int32_t monotone, nr_mbir* out) {
+  if (!out) return fail(NR_INVALID_ARG, "nr_mbir_params: out is NULL");
+  if (!(lipschitz_data >= 0.0) || !std::isfinite(lipschitz_data))
+    return fail(NR_INVALID_ARG, "nr_mbir_params: the data term's Lipschitz constant must be finite and >= 0");
+  double lh = 0.0;
+  if (prior)
+    if (nr_status st = nr_prior_lipschitz(prior, &lh)) return st;
+  const double L = lipschitz_data + lh;
+  if (!(L > 0.0)) return fail(NR_INVALID_ARG, "nr_mbir_params: L = L_R + L_H must be > 0");
+  *out = nr_mbir{float(1.0 / L), restart, nonneg, monotone};
+  return check_mbir(out);
+}
+
+nr_status nr_power_lipschitz(nr_plan* plan, int32_t iters, uint64_t seed, double safety, float* d_v, float* d_w,
+                             float* d_sino, double* d_work, double* h_out, nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!d_v || !d_w || !d_sino || !d_work || !h_out) return fail(NR_INVALID_ARG, "nr_power_lipschitz: NULL argument");
+  if (d_v == d_w) return fail(NR_INVALID_ARG, "nr_power_lipschitz: d_v and d_w must differ");
+  if (iters < 1 || !(safety >= 1.0) || !std::isfinite(safety))
+    return fail(NR_INVALID_ARG, "nr_power_lipschitz: iters >= 1 and finite safety >= 1");
+  if (nr_status st = pending_error("before nr_power_lipschitz")) return st;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const nr::Plan& p = plan->p;
+  const size_t ext = vol_extent(p);
+  // v: seeded uniform values on every slice, zero between slices; w starts at
+  // zero so that cells outside the slices stay zero
+  hipError_t e = nrk::launch_fill_value(d_v, ext, 0.f, st);
+  if (e == hipSuccess) e = nrk::launch_fill_value(d_w, ext, 0.f, st);
+  for (const nr_slice& sl : p.slices)
+    if (e == hipSuccess)
+      e = nrk::launch_fill_random(d_v + sl.vol_off, size_t(sl.n) * sl.n, seed, uint64_t(sl.vol_off), st);
+  if (e == hipSuccess) e = nrk::launch_normalize(d_v, d_v, ext, d_work, st);
+  if (e != hipSuccess) return hip_fail(e, "nr_power_lipschitz start");
+  for (int k = 0; k < iters; ++k) {
+    // w = R^T R v, then v = w / ||w||, ||w||^2 left in d_work
+    if (nr_status s = radon_normal(plan, d_v, nullptr, d_sino, d_w, stream)) return s;
+    e = nrk::launch_normalize(d_v, d_w, ext, d_work, st);
+    if (e != hipSuccess) return hip_fail(e, "nr_power_lipschitz step");
+  }
+  double ss = 0.0;
+  e = hipMemcpyAsync(&ss, d_work, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "nr_power_lipschitz read-back");
+  if (!std::isfinite(ss)) return fail(NR_NONFINITE, "nr_power_lipschitz: non-finite norm");
+  *h_out = safety * std::sqrt(ss);
+  return NR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+nr_status nr_plan_get_tune(const nr_plan* plan, const char* key, int64_t* value) {
+  if (!plan || !key || !value) return fail(NR_INVALID_ARG, "nr_plan_get_tune: NULL argument");
+  const std::string k = key;
+  if (k == "autotune_us") {
+    *value = plan->tune_best_ms < 0.0 ? -1 : int64_t(std::llround(plan->tune_best_ms * 1e3));
+    return NR_OK;
+  }
+  if (k == "autotune_trials") {
+    *value = plan->tune_trials;
+    return NR_OK;
+  }
+  const int64_t v = tune_value(plan->p.tune, k);
+  if (v == INT64_MIN) return fail(NR_INVALID_ARG, "nr_plan_get_tune: unknown key " + k);
+  *value = v;
+  return NR_OK;
+}
+
+nr_status nr_autotune_scratch_bytes(nr_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(NR_INVALID_ARG, "nr_autotune_scratch_bytes: NULL argument");
+  const nr::Tuning keep = plan->p.tune;
+  const bool was_laid_out = plan->p.laid_out;
+  size_t most = 0, tables = 0, b = 0;
+  nr_status st = NR_OK;
+  // the slot areas of every batch budget and stream count at the current tile
+  for (int mb : kTuneBudgets)
+    for (int ns : kTuneStreams) {
+      nr::Tuning t = keep;
+      t.batch_mb = mb;
+      t.streams = ns;
+      if ((st = layout_bytes(plan, t, b)) != NR_OK) break;
+      most = std::max(most, b);
+    }
+  // and the tables of every tile shape at the smallest item size
+  for (const auto& tw : kTuneTiles) {
+    if (st != NR_OK) break;
+    nr::Tuning t = keep;
+    t.tile_w = tw[0];
+    t.tile_h = tw[1];
+    t.chunk = kTuneChunks[0];
+    if ((st = layout_bytes(plan, t, b)) != NR_OK) break;
+    tables = std::max(tables, plan->p.off_slot);
+  }
+  plan->p.tune = keep;
+  plan->p.laid_out = false;
+  std::string err;
+  if (was_laid_out || st == NR_OK) (void)nr::layout_plan(plan->p, err);
+  if (st != NR_OK) return st;
+  *bytes = tune_buffer_bytes(plan->p) + most + tables + (size_t(1) << 20);
+  return NR_OK;
+}
+
+nr_status nr_autotune(nr_plan* plan, void* d_scratch, size_t bytes, const char* cache_json, nr_stream stream) {
+  if (!plan || !d_scratch) return fail(NR_INVALID_ARG, "nr_autotune: plan/scratch is NULL");
+  if (reinterpret_cast<uintptr_t>(d_scratch) % 256 != 0) return fail(NR_INVALID_ARG, "nr_autotune: scratch not 256-byte aligned");
+  if (nr_status st = pending_error("before nr_autotune")) return st;
+  // the plan is unbound from here on (its workspace may already be released)
+  plan->p.d_ws = nullptr;
+  plan->p.d_ws_bytes = 0;
+  plan->gen = next_generation();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "nr_autotune device");
+  nr::Plan& p = plan->p;
+  const std::string key = geometry_key(p, std::string(prop.name) + "/" + prop.gcnArchName);
+  // a cached tuning for this geometry and device: apply it, no timing
+  Cache cache;
+  if (cache_json) {
+    std::ifstream f(cache_json);
+    if (f) {
+      std::stringstream ss;
+      ss << f.rdbuf();
+      (void)parse_cache(ss.str(), cache);
+    }
+    for (const auto& kv : cache)
+      if (kv.first == key) {
+        nr::Tuning t = p.tune;
+        double ms = -1.0;
+        for (const auto& f2 : kv.second) {
+          if (f2.first == "ms") ms = f2.second;
+          else set_tune_value(t, f2.first, int64_t(f2.second));
+        }
+        size_t b = 0;
+        if (nr_status s = layout_bytes(plan, t, b)) return s;
+        p.d_ws = nullptr;
+        p.d_ws_bytes = 0;
+        plan->gen = next_generation();
+        plan->tune_best_ms = ms;
+        plan->tune_trials = 0;
+        return NR_OK;
+      }
+  }
+  // buffers of the timed passes, then the candidate's workspace
+  const size_t nv = vol_extent(p), ns = sino_extent(p);
+  char* base = static_cast<char*>(d_scratch);
+  float* vol = reinterpret_cast<float*>(base);
+  float* back = reinterpret_cast<float*>(base + align256(nv * sizeof(float)));
+  float* sino = reinterpret_cast<float*>(base + 2 * align256(nv * sizeof(float)));
+  const size_t used = tune_buffer_bytes(p);
+  if (bytes < used + 256) return fail(NR_WORKSPACE_TOO_SMALL, "nr_autotune: scratch smaller than one pass's buffers");
+  char* ws = base + used;
+  const size_t ws_room = bytes - used;
+  e = nrk::launch_fill_random(vol, nv, 0x5eedull, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "nr_autotune fill");
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(e, "nr_autotune events");
+  }
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  const int reps = 3;
+  int trials = 0;
+  // one forward + adjoint pass per repetition under tuning t; +inf when the
+  // workspace does not fit the scratch
+  auto time_of = [&](const nr::Tuning& t, double& ms) -> nr_status {
+    ms = HUGE_VAL;
+    size_t need = 0;
+    if (nr_status s = layout_bytes(plan, t, need)) return s;
+    if (need > ws_room) return NR_OK;
+    if (nr_status s = nr_plan_bind(plan, ws, ws_room, stream)) return s;
+    if (nr_status s = radon_normal(plan, vol, nullptr, sino, back, stream)) return s;   // warm-up
+    hipError_t he = hipEventRecord(t0, st);
+    for (int r = 0; r < reps && he == hipSuccess; ++r)
+      if (nr_status s = radon_normal(plan, vol, nullptr, sino, back, stream)) return s;
+    if (he == hipSuccess) he = hipEventRecord(t1, st);
+    if (he == hipSuccess) he = hipEventSynchronize(t1);
+    float el = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&el, t0, t1);
+    if (he != hipSuccess) return hip_fail(he, "nr_autotune timing");
+    ms = double(el) / reps;
+    ++trials;
+    return NR_OK;
+  };
+  // coordinate search from the plan's current setting, one parameter at a time
+  nr::Tuning best = p.tune;
+  double best_ms = HUGE_VAL;
+  nr_status status = time_of(best, best_ms);
+  auto consider = [&](nr::Tuning t) {
+    double ms = HUGE_VAL;
+    if (status == NR_OK) status = time_of(t, ms);
+    if (status == NR_OK && ms < best_ms) best = t, best_ms = ms;
+  };
+  for (int mb : kTuneBudgets)
+    if (mb != best.batch_mb) { nr::Tuning t = best; t.batch_mb = mb; consider(t); }
+  for (int n : kTuneStreams)
+    if (n != best.streams) { nr::Tuning t = best; t.streams = n; consider(t); }
+  for (const auto& tw : kTuneTiles)
+    if (tw[0] != best.tile_w || tw[1] != best.tile_h) { nr::Tuning t = best; t.tile_w = tw[0]; t.tile_h = tw[1]; consider(t); }
+  for (int c : kTuneChunks)
+    if (c != best.chunk) { nr::Tuning t = best; t.chunk = c; consider(t); }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  plan->profiling = prof;
+  // the plan keeps the best setting, unbound (the scratch was the caller's)
+  size_t b = 0;
+  if (status == NR_OK) status = layout_bytes(plan, best, b);
+  p.d_ws = nullptr;
+  p.d_ws_bytes = 0;
+  plan->gen = next_generation();
+  if (status != NR_OK) return status;
+  if (!(best_ms < HUGE_VAL)) return fail(NR_WORKSPACE_TOO_SMALL, "nr_autotune: no candidate fits the scratch");
+  plan->tune_best_ms = best_ms;
+  plan->tune_trials = trials;
+  if (cache_json) {
+    CacheEntry entry;
+    for (const char* k : kTuneKeys) entry.emplace_back(k, double(tune_value(best, k)));
+    entry.emplace_back("ms", best_ms);
+    bool found = false;
+    for (auto& kv : cache)
+      if (kv.first == key) kv.second = entry, found = true;
+    if (!found) cache.emplace_back(key, entry);
+    const std::string tmp = std::string(cache_json) + ".tmp";
+    {
+      std::ofstream f(tmp, std::ios::trunc);
+      if (!f) return fail(NR_INVALID_ARG, std::string("nr_autotune: cannot write ") + tmp);
+      f << format_cache(cache);
+    }
+    if (std::rename(tmp.c_str(), cache_json) != 0)
+      return fail(NR_INVALID_ARG, std::string("nr_autotune: cannot replace ") + cache_json);
   }
   return NR_OK;
 }

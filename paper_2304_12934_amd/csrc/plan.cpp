@@ -245,8 +245,10 @@ void build_spread_bins(const Plan& plan, Geom& g) {
           for (int l = std::max(0, cc0); l < std::min(g.tile_w, cc0 + W); ++l)
             cmax = std::max(cmax, ++cell_count[size_t(i) * g.tile_w + l]);
       }
+      // (the origin's k = 0 sum is added in float32 at write-out, outside the
+      // fixed-point sums)
       const int flags = (n_items > 1 ? kItemAtomic : 0) | (has_dc && k == 0 ? kItemDC : 0);
-      g.items.push_back({t, ib, ie, flags, cmax + ((flags & kItemDC) ? 1 : 0) + 1});
+      g.items.push_back({t, ib, ie, flags, cmax + 1});
     }
   }
   // heaviest items first so the long ones start early
@@ -479,12 +481,22 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     return NR_INVALID_ARG;
   }
   for (Geom& g : plan.geoms) {
-    build_spread_bins(plan, g);
-    if (tu.interp_mode == 0) build_interp_bins(plan, g);
-    else {
+    if (g.bins_tile_w != tu.tile_w || g.bins_tile_h != tu.tile_h || g.bins_chunk != tu.chunk) {
+      build_spread_bins(plan, g);
+      g.bins_tile_w = tu.tile_w;
+      g.bins_tile_h = tu.tile_h;
+      g.bins_chunk = tu.chunk;
+    }
+    if (tu.interp_mode == 0) {
+      if (g.ibins_chunk != tu.chunk) {
+        build_interp_bins(plan, g);
+        g.ibins_chunk = tu.chunk;
+      }
+    } else {
       g.itiles_x = g.itiles_y = 0;
       g.ipts.clear();
       g.iitems.clear();
+      g.ibins_chunk = -1;
     }
   }
 

@@ -75,6 +75,9 @@ struct Geom {
   int itiles_x = 0, itiles_y = 0;
   std::vector<int32_t> ipts;
   std::vector<SpreadItem> iitems;
+  // tuning the bins were last built for (layouts that change only the
+  // batching reuse them)
+  int bins_tile_w = -1, bins_tile_h = -1, bins_chunk = -1, ibins_chunk = -1;
   // workspace offsets (bytes)
   size_t off_gxy = 0, off_flip = 0, off_pts = 0, off_items = 0, off_zero = 0, off_ipts = 0, off_iitems = 0;
 };

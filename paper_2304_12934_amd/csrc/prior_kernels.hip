@@ -160,7 +160,7 @@ __device__ __forceinline__ void qggmrf_block(const float* __restrict__ f, float*
   direction<VALUE, INTERIOR, 1, 1, 1>(b, F, R1, fc, acc, hsum, pr);
   const float gscale = scale * 2.f * pr.lambda * b.inv_sigma;
   const int x = b.x0 + b.lx, y = b.y0 + b.ly;
-  if (x < b.n && y < b.n) {
+  if (grad && x < b.n && y < b.n) {   // no gradient output: the value alone
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
       if (b.z0 + z < b.nz) grad[size_t(b.z0 + z) * plane + size_t(y) * b.n + x] += gscale * acc[z];
@@ -221,10 +221,11 @@ __global__ __launch_bounds__(256) void k_residual_norm(float* __restrict__ s, co
   if (threadIdx.x == 0) atomicAdd(value, 0.5 * red[0]);
 }
 
-// <g, x' - x> with x' = y - g/L (clamped at 0 when nonneg); non-finite flag
+// <g, x' - x> with x' = y - g/L (clamped at 0 when nonneg); non-finite flag.
+// With cand, x' is also stored there (the monotone step evaluates it).
 __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, const float* __restrict__ y,
                                                   const float* __restrict__ g, size_t count, float inv_L,
-                                                  int nonneg, double* state) {
+                                                  int nonneg, double* state, float* __restrict__ cand) {
   __shared__ double red[256];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, c
     if (nonneg) xn = fmaxf(xn, 0.f);
     acc += double(gi) * double(xn - x[i]);
     if (!isfinite(gi) || !isfinite(xn)) nf = 1;
+    if (cand) cand[i] = xn;
   }
   if (nf) bad = 1;
   red[threadIdx.x] = acc;
@@ -246,21 +248,37 @@ __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, c
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(&state[1], red[0]);
-    if (bad) state[2] = 1.0;
+    atomicAdd(&state[kStDot], red[0]);
+    if (bad) state[kStNonfinite] = 1.0;
   }
 }
 
-// restart test and momentum: t <- 1 if <g, x'-x> > 0; t' = (1+sqrt(1+4t^2))/2; beta = (t-1)/t'
-__global__ void k_mbir_finalize(double* state) {
-  double t = state[0];
-  if (state[1] > 0.0) {
+// Restart test and momentum: t <- 1 if <g, x'-x> > 0 (when restart is on);
+// with monotone, the candidate x' is rejected (x kept, t <- 1, no momentum)
+// when its objective exceeds that of x (the first step, with no objective
+// recorded yet, is accepted); t' = (1 + sqrt(1 + 4t^2))/2, beta = (t - 1)/t'.
+__global__ void k_mbir_finalize(double* state, int restart, int monotone) {
+  double t = state[kStT];
+  if (restart && state[kStDot] > 0.0) {
     t = 1.0;
-    state[3] += 1.0;
+    state[kStRestarts] += 1.0;
+  }
+  double accept = 1.0;
+  if (monotone) {
+    const double phi = state[kStPhiData] + state[kStPhiPrior];
+    if (state[kStPhiKnown] != 0.0 && !(phi <= state[kStPhiX])) {
+      accept = 0.0;
+      t = 1.0;
+      state[kStRejects] += 1.0;
+    } else {
+      state[kStPhiX] = phi;
+      state[kStPhiKnown] = 1.0;
+    }
   }
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-  state[4] = (t - 1.0) / tn;
-  state[0] = tn;
+  state[kStBeta] = accept != 0.0 ? (t - 1.0) / tn : 0.0;
+  state[kStT] = tn;
+  state[kStAccepted] = accept;
 }
 
 // x' = y - g/L; y <- x' + beta (x' - x); x_prev <- x; x <- x'
@@ -268,7 +286,7 @@ __global__ __launch_bounds__(256) void k_mbir_update(float* __restrict__ x, floa
                                                      float* __restrict__ y, const float* __restrict__ g,
                                                      size_t count, float inv_L, int nonneg,
                                                      const double* __restrict__ state) {
-  const float beta = float(state[4]);
+  const float beta = float(state[kStBeta]);
   for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
     float xn = y[i] - inv_L * g[i];
     if (nonneg) xn = fmaxf(xn, 0.f);
@@ -277,6 +295,74 @@ __global__ __launch_bounds__(256) void k_mbir_update(float* __restrict__ x, floa
     x_prev[i] = xo;
     x[i] = xn;
   }
+}
+
+// Monotone update, the candidate x' held in x_prev: accepted, x <- x',
+// x_prev <- x, y <- x' + beta (x' - x); rejected, x stays and y = x_prev = x.
+__global__ __launch_bounds__(256) void k_mbir_update_mono(float* __restrict__ x, float* __restrict__ x_prev,
+                                                          float* __restrict__ y, size_t count,
+                                                          const double* __restrict__ state) {
+  const float beta = float(state[kStBeta]);
+  const bool accept = state[kStAccepted] != 0.0;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
+    const float xo = x[i], xn = x_prev[i];
+    if (accept) {
+      y[i] = xn + beta * (xn - xo);
+      x[i] = xn;
+    } else {
+      y[i] = xo;
+    }
+    x_prev[i] = xo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// power iteration for the largest eigenvalue of R^T R
+// ---------------------------------------------------------------------------
+
+// uniform in [-1, 1) from a counter-based generator: splitmix64 of
+// (seed, index), the published finaliser of Steele, Lea and Flood (2014)
+__device__ __forceinline__ float uniform_pm1(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return float(int64_t(z >> 40) - (int64_t(1) << 23)) * (1.0f / float(1 << 23));
+}
+
+__global__ __launch_bounds__(256) void k_fill_random(float* __restrict__ v, size_t count, uint64_t seed,
+                                                     uint64_t first) {
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256)
+    v[i] = uniform_pm1(seed, first + i);
+}
+
+__global__ __launch_bounds__(256) void k_fill_value(float* __restrict__ v, size_t count, float value) {
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) v[i] = value;
+}
+
+// *out += scale * sum v^2 (float64)
+__global__ __launch_bounds__(256) void k_sum_squares(const float* __restrict__ v, size_t count, double* out,
+                                                     double scale) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256)
+    acc += double(v[i]) * double(v[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, scale * red[0]);
+}
+
+// v = w / sqrt(*ss) (a zero norm leaves v = 0)
+__global__ __launch_bounds__(256) void k_scale_inv_norm(float* __restrict__ v, const float* __restrict__ w,
+                                                        size_t count, const double* __restrict__ ss) {
+  const double n2 = *ss;
+  const float inv = n2 > 0.0 ? float(1.0 / sqrt(n2)) : 0.f;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256)
+    v[i] = w[i] * inv;
 }
 
 hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int n, const PriorArgs& pr,
@@ -301,11 +387,66 @@ hipError_t launch_residual_norm(float* s, const float* b, size_t count, double* 
 }
 
 hipError_t launch_mbir_update(float* x, float* x_prev, float* y, const float* g, size_t count, float inv_L,
-                              int nonneg, double* state, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, state + 1, 0.0);
-  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state);
-  hipLaunchKernelGGL(k_mbir_finalize, dim3(1), dim3(1), 0, st, state);
+                              int nonneg, int restart, double* state, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, state + kStDot, 0.0);
+  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state,
+                     static_cast<float*>(nullptr));
+  hipLaunchKernelGGL(k_mbir_finalize, dim3(1), dim3(1), 0, st, state, restart, 0);
   hipLaunchKernelGGL(k_mbir_update, dim3(4096), dim3(256), 0, st, x, x_prev, y, g, count, inv_L, nonneg, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbir_candidate(const float* x, float* x_prev, const float* y, const float* g, size_t count,
+                                 float inv_L, int nonneg, double* state, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, state + kStDot, 0.0);
+  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state, x_prev);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbir_finish_monotone(float* x, float* x_prev, float* y, size_t count, int restart, double* state,
+                                       hipStream_t st) {
+  hipLaunchKernelGGL(k_mbir_finalize, dim3(1), dim3(1), 0, st, state, restart, 1);
+  hipLaunchKernelGGL(k_mbir_update_mono, dim3(4096), dim3(256), 0, st, x, x_prev, y, count,
+                     static_cast<const double*>(state));
+  return hipGetLastError();
+}
+
+__global__ void k_mbir_state_init(double* state) {
+  if (threadIdx.x < kStCount) state[threadIdx.x] = threadIdx.x == kStT ? 1.0 : 0.0;
+}
+
+hipError_t launch_mbir_state_init(double* state, hipStream_t st) {
+  hipLaunchKernelGGL(k_mbir_state_init, dim3(1), dim3(64), 0, st, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(float* v, size_t count, uint64_t seed, uint64_t first, hipStream_t st) {
+  const size_t blocks = std::min<size_t>(4096, std::max<size_t>(1, (count + 255) / 256));
+  hipLaunchKernelGGL(k_fill_random, dim3(unsigned(blocks)), dim3(256), 0, st, v, count, seed, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_value(float* v, size_t count, float value, hipStream_t st) {
+  const size_t blocks = std::min<size_t>(4096, std::max<size_t>(1, (count + 255) / 256));
+  hipLaunchKernelGGL(k_fill_value, dim3(unsigned(blocks)), dim3(256), 0, st, v, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_sum_squares(const float* v, size_t count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, out, 0.0);
+  hipLaunchKernelGGL(k_sum_squares, dim3(2048), dim3(256), 0, st, v, count, out, 0.5);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_double(double* p, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(float* v, const float* w, size_t count, double* ss, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, ss, 0.0);
+  hipLaunchKernelGGL(k_sum_squares, dim3(2048), dim3(256), 0, st, w, count, ss, 1.0);
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(4096), dim3(256), 0, st, v, w, count, static_cast<const double*>(ss));
   return hipGetLastError();
 }
 

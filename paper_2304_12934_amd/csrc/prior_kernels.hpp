@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace nrk {
 
 struct PriorArgs {
@@ -17,8 +19,42 @@ hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int
 hipError_t launch_residual(float* s, const float* b, size_t count, hipStream_t st);
 // s -= b and value = 1/2 sum (s - b)^2
 hipError_t launch_residual_norm(float* s, const float* b, size_t count, double* value, hipStream_t st);
-// restart test, momentum and the x/y update; state = {t, dot, nonfinite, restarts, beta, ...}
+// Slots of the float64 MBIR state array (kStCount doubles on the device).
+enum {
+  kStT = 0,          // momentum parameter t_k
+  kStDot,            // <g, x' - x> of the last step
+  kStNonfinite,      // 1 once a NaN/Inf appeared
+  kStRestarts,       // momentum restarts so far (gradient test and rejected steps)
+  kStBeta,           // momentum coefficient of the last step
+  kStPhiX,           // objective at x (monotone steps)
+  kStPhiKnown,       // 1 once kStPhiX holds a value
+  kStPhiData,        // data term at the last candidate
+  kStPhiPrior,       // prior at the last candidate
+  kStAccepted,       // 1 if the last candidate was accepted
+  kStRejects,        // candidates rejected by the monotone test
+  kStCount = 16
+};
+
+// restart test (restart != 0), momentum and the x/y update
 hipError_t launch_mbir_update(float* x, float* x_prev, float* y, const float* g, size_t count, float inv_L,
-                              int nonneg, double* state, hipStream_t st);
+                              int nonneg, int restart, double* state, hipStream_t st);
+// monotone step, first half: the restart dot product and the candidate
+// x' = y - g/L (clamped when nonneg) into x_prev
+hipError_t launch_mbir_candidate(const float* x, float* x_prev, const float* y, const float* g, size_t count,
+                                 float inv_L, int nonneg, double* state, hipStream_t st);
+// monotone step, second half (the candidate's objective already in the
+// state): accept or reject, momentum, x/x_prev/y update
+hipError_t launch_mbir_finish_monotone(float* x, float* x_prev, float* y, size_t count, int restart, double* state,
+                                       hipStream_t st);
+// t = 1, every other slot 0
+hipError_t launch_mbir_state_init(double* state, hipStream_t st);
+// v[i] = uniform in [-1, 1) from (seed, first + i); v[i] = value
+hipError_t launch_fill_random(float* v, size_t count, uint64_t seed, uint64_t first, hipStream_t st);
+hipError_t launch_fill_value(float* v, size_t count, float value, hipStream_t st);
+// *out = 1/2 sum v^2 (float64); *p = v
+hipError_t launch_half_sum_squares(const float* v, size_t count, double* out, hipStream_t st);
+hipError_t launch_set_double(double* p, double v, hipStream_t st);
+// *ss = sum w^2 (float64), then v = w / sqrt(*ss)
+hipError_t launch_normalize(float* v, const float* w, size_t count, double* ss, hipStream_t st);
 
 }  // namespace nrk

@@ -345,6 +345,34 @@ __device__ __forceinline__ float2 interp_point(const DSlice& d, int halo, int co
   return acc;
 }
 
+// The two sinogram rows a0, a0 + 1 (the second when has1) from the packed
+// inverse transform in s (real part: row a0, imaginary part: row a0 + 1):
+// bin m (t = m - N_t/2) is output index t mod N_t.  With a.sino_sub the
+// data b are subtracted as the rows are stored (the residual R f - b of the
+// data term, Sec. 3 eq. "objfn"), so no separate pass re-reads them.
+template <int L, int T>
+__device__ __forceinline__ void store_sino_rows(const LaunchArgs& a, const DSlice& d, int a0, bool has1, Lds s,
+                                                int tid) {
+  const size_t off = d.sino_off + size_t(a0) * L;
+  float* __restrict__ o0 = a.sino_out + off;
+  if (a.sino_sub) {
+    const float* __restrict__ b0 = a.sino_sub + off;
+    const float* __restrict__ b1 = has1 ? b0 + L : b0;   // loads stay unconditional
+    NR_STRIDED(m, L, T) {
+      const float2 z = s[wrap_index<L>(m + L / 2)];
+      const float c0 = b0[m], c1 = b1[m];
+      o0[m] = z.x - c0;
+      if (has1) o0[L + m] = z.y - c1;
+    }
+  } else {
+    NR_STRIDED(m, L, T) {
+      const float2 z = s[wrap_index<L>(m + L / 2)];
+      o0[m] = z.x;
+      if (has1) o0[L + m] = z.y;
+    }
+  }
+}
+
 template <int L, int W>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBArgs kb) {
   constexpr int T = fft_threads(L);
@@ -371,12 +399,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
     __syncthreads();
     fft_lds<L, T, true>(s, d.tw_Nt, tid);
     // bin m (t = m - N_t/2) is output index t mod N_t
-    float* __restrict__ o0 = a.sino_out + d.sino_off + size_t(a0) * L;
-    NR_STRIDED(m, L, T) {
-      const float2 z = s[wrap_index<L>(m + L / 2)];
-      o0[m] = z.x;
-      if (has1) o0[L + m] = z.y;
-    }
+    store_sino_rows<L, T>(a, d, a0, has1, s, tid);
     __syncthreads();
   }
 }
@@ -496,12 +519,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
     }
     __syncthreads();
     fft_lds<L, T, true>(s, d.tw_Nt, tid);
-    float* __restrict__ o0 = a.sino_out + d.sino_off + size_t(a0) * L;
-    NR_STRIDED(m, L, T) {
-      const float2 z = s[wrap_index<L>(m + L / 2)];
-      o0[m] = z.x;
-      if (has1) o0[L + m] = z.y;
-    }
+    store_sino_rows<L, T>(a, d, a0, has1, s, tid);
     __syncthreads();
   }
 }
@@ -646,7 +664,10 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
     const int r0 = (it.tile / d.tiles_x) * TH, c0 = (it.tile % d.tiles_x) * TW;
     // apron coordinates of grid cell (row g0x + halo, column g0y + G/2 + colpad)
     const int rbase = a.halo - r0 + W, cbase = d.G / 2 + a.colpad - c0 + W;
-    // k = 0 of every angle sits at the origin: their sum is spread once
+    // k = 0 of every angle sits at the origin: their sum is spread once, in
+    // float32 when the tile is written out, so that it does not enter the
+    // item's fixed-point scale (with many angles it is far larger than any
+    // single point value and would coarsen every other contribution)
     float dc = 0.f;
     if (it.flags & kItemDC) {
       float sum = 0.f;
@@ -665,16 +686,9 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
       }
     }
     if (tid == 0) nonfinite = 0;
-    const float mmax = fmaxf(block_max<T>(m, red), fabsf(dc));   // synchronises: the tile is cleared
+    const float mmax = block_max<T>(m, red);   // synchronises: the tile is cleared
     if (bad) nonfinite = 1;
     const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
-    if ((it.flags & kItemDC) && tid < W * W) {
-      int g0x, g0y;
-      float wx[W], wy[W];
-      point_taps<W>(0.0, 0.0, 0, kb, g0x, g0y, wx, wy);
-      const int i = tid / W, l = tid % W;
-      atomicAdd(&acc_re[(g0x + i + rbase) * TS + g0y + l + cbase], round_half_up(q * dc * wx[i] * wy[l]));
-    }
     // one point per round; the slot's registers are picked with compile-time
     // indices (no dynamic register indexing) and the taps are unrolled once
 #pragma unroll 1
@@ -715,6 +729,15 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
     __syncthreads();
     const bool shared_tile = it.flags & kItemAtomic;
     const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
+    // the origin's W x W footprint in apron coordinates (DC items only)
+    int dcx = 0, dcy = 0;
+    float dwx[W], dwy[W];
+    const bool has_dc = it.flags & kItemDC;
+    if (has_dc) {
+      point_taps<W>(0.0, 0.0, 0, kb, dcx, dcy, dwx, dwy);
+      dcx += rbase;
+      dcy += cbase;
+    }
     NR_G float2* ext = d.ext;
     for (int c = tid; c < TH * TW; c += T) {
       const int rl = c / TW, cl = c % TW;
@@ -722,7 +745,20 @@ __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
       if (r >= d.rows || cc >= d.cols) continue;
       NR_G float2* dst = ext + size_t(r) * d.cols + cc;
       const int ai = (rl + W) * TS + cl + W;
-      const float re = float(acc_re[ai]) * inv_q, im = float(acc_im[ai]) * inv_q;
+      float re = float(acc_re[ai]) * inv_q;
+      const float im = float(acc_im[ai]) * inv_q;
+      if (has_dc) {
+        const int i = rl + W - dcx, l = cl + W - dcy;
+        if (i >= 0 && i < W && l >= 0 && l < W) {
+          float wi = 0.f, wl = 0.f;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {   // compile-time register indices
+            if (k == i) wi = dwx[k];
+            if (k == l) wl = dwy[k];
+          }
+          re += dc * wi * wl;
+        }
+      }
       if (shared_tile) {
         atomicAdd((float*)&dst->x, re);
         atomicAdd((float*)&dst->y, im);

@@ -17,6 +17,7 @@ struct LaunchArgs {
   float* vol_out;
   const float* sino_in;
   float* sino_out;
+  const float* sino_sub;    // subtracted from the forward's output (residual R f - b) when not null
   int fbp_filter;           // adjoint radial weight: -1 none, 0 ramp, 1 ramp x Butterworth
   int fbp_order;
   float fbp_inv_cutoff;

@@ -7,17 +7,35 @@ arithmetic of the method runs here.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
-import math
-from dataclasses import dataclass, field
+import sys
+import weakref
+from dataclasses import dataclass
 from typing import Sequence
 
 import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (NR_FBP_BUTTERWORTH, NR_FBP_RAMP, NR_STREAM_ADJ, NR_STREAM_FBP, NR_STREAM_FWD, NrFbp, NrMbir,
-                   NrNufft, NrPrior, NrSlice, check, lib)
+from ._lib import (NR_FBP_BUTTERWORTH, NR_FBP_RAMP, NR_MBIR_STATE_DOUBLES, NR_STREAM_ADJ, NR_STREAM_FBP,
+                   NR_STREAM_FWD, NR_WEIGHTS_GAUSSIAN, NR_WEIGHTS_INV_DISTANCE, NrFbp, NrMbir, NrNufft, NrPrior,
+                   NrSlice, check, lib)
+
+# Plans and graphs still open, closed at interpreter exit while the HIP
+# runtime is alive (their streams and graphs are HIP objects); a handle whose
+# owner is collected during interpreter finalisation is left to the process
+# exit instead of being destroyed then.
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live() -> None:
+    for obj in sorted(list(_LIVE), key=lambda o: 0 if isinstance(o, Graph) else 1):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:
@@ -97,6 +115,7 @@ class Plan:
                                self._angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                ctypes.byref(params), ctypes.byref(handle)), "nr_plan_create")
         self._h = handle
+        _LIVE.add(self)
         self.tuning = {}
         self._ws = None
         self.retune(**(tuning or {}))
@@ -113,6 +132,11 @@ class Plan:
             self.tuning[k] = int(v)
         if self._ws is not None and set(kw) <= {"spread_mode"}:
             return
+        self._bind()
+
+    def _bind(self) -> None:
+        """Allocate a workspace of the size the current layout needs and bind it."""
+        L = lib()
         nbytes = ctypes.c_size_t()
         check(L.nr_plan_workspace_bytes(self._h, ctypes.byref(nbytes)), "nr_plan_workspace_bytes")
         self.workspace_bytes = int(nbytes.value)
@@ -122,6 +146,35 @@ class Plan:
         ws_ptr = ctypes.c_void_p(self._ws.data_ptr() + off)
         with torch.cuda.device(self.device):
             check(L.nr_plan_bind(self._h, ws_ptr, self.workspace_bytes, _stream(self.device)), "nr_plan_bind")
+
+    def autotune(self, cache_path: str | None = None) -> dict:
+        """Pick the execution parameters by timing candidates on the device
+        (``nr_autotune``: batch budget, streams, spreading tile and item size,
+        one at a time), cached per geometry and device in ``cache_path``
+        (JSON; None: no cache), then rebind.  Returns the chosen tuning."""
+        L = lib()
+        need = ctypes.c_size_t()
+        check(L.nr_autotune_scratch_bytes(self._h, ctypes.byref(need)), "nr_autotune_scratch_bytes")
+        self._ws = None                      # the tuner lays out and binds its own candidates
+        torch.cuda.empty_cache()
+        try:
+            scratch = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=self.device)
+            ptr = ctypes.c_void_p(scratch.data_ptr() + (-scratch.data_ptr()) % 256)
+            with torch.cuda.device(self.device):
+                check(L.nr_autotune(self._h, ptr, int(need.value), cache_path.encode() if cache_path else None,
+                                    _stream(self.device)), "nr_autotune")
+            del scratch
+            torch.cuda.empty_cache()
+        finally:
+            # whatever happened, the plan gets a workspace of its current layout back
+            self._bind()
+        self.tuning = {k: self.get_tune(k) for k in ("tile_w", "tile_h", "chunk", "batch_mb", "streams")}
+        return dict(self.tuning)
+
+    def get_tune(self, key: str) -> int:
+        v = ctypes.c_int64()
+        check(lib().nr_plan_get_tune(self._h, key.encode(), ctypes.byref(v)), "nr_plan_get_tune")
+        return int(v.value)
 
     def capture(self, what: str, vol_in: torch.Tensor | None = None, sino: torch.Tensor | None = None,
                 vol_out: torch.Tensor | None = None) -> "Graph":
@@ -286,14 +339,28 @@ class Plan:
         keys = ("G", "tiles", "tile_entries", "spread_items", "poly_degree", "slots", "batches", "launches")
         return dict(zip(keys, list(buf)))
 
-    def __del__(self):
+    def close(self) -> None:
+        """Destroy the plan (its streams and events) now; the workspace is
+        released with the Python object."""
         h = getattr(self, "_h", None)
+        self._h = None
+        _LIVE.discard(self)
         if h is not None and h.value:
+            lib().nr_plan_destroy(h)
+
+    def __enter__(self) -> "Plan":
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self.close()
+
+    def __del__(self):
+        # at interpreter shutdown the process exit releases the handle
+        if not sys.is_finalizing():
             try:
-                lib().nr_plan_destroy(h)
+                self.close()
             except Exception:
                 pass
-            self._h = None
 
 
 class Graph:
@@ -301,45 +368,69 @@ class Graph:
 
     def __init__(self, handle: ctypes.c_void_p, plan: Plan, keep: tuple):
         self._h, self.plan, self._keep = handle, plan, keep
+        _LIVE.add(self)
 
     def launch(self) -> None:
         with torch.cuda.device(self.plan.device):
             check(lib().nr_graph_launch(self._h, _stream(self.plan.device)), "nr_graph_launch")
 
-    def __del__(self):
+    def close(self) -> None:
         h = getattr(self, "_h", None)
+        self._h = None
+        _LIVE.discard(self)
         if h is not None and h.value:
+            lib().nr_graph_destroy(h)
+
+    def __enter__(self) -> "Graph":
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self.close()
+
+    def __del__(self):
+        if not sys.is_finalizing():
             try:
-                lib().nr_graph_destroy(h)
+                self.close()
             except Exception:
                 pass
-            self._h = None
 
 
 # --------------------------------------------------------------------------
 # prior
 # --------------------------------------------------------------------------
 
-def _inverse_distance_weights():
-    total = 6.0 + 12.0 / math.sqrt(2.0) + 8.0 / math.sqrt(3.0)
-    return 1.0 / total, (1.0 / math.sqrt(2.0)) / total, (1.0 / math.sqrt(3.0)) / total
+_WEIGHT_KINDS = {"inv_distance": NR_WEIGHTS_INV_DISTANCE, "gaussian": NR_WEIGHTS_GAUSSIAN}
 
 
 @dataclass
 class Prior:
-    """qGGMRF hyper-parameters (defaults: the paper's p = 1.2, sigma = 1/0.7, c = 1e-4)."""
+    """qGGMRF hyper-parameters (defaults: the paper's p = 1.2, sigma = 1/0.7, c = 1e-4).
+
+    ``weights``: ``"inv_distance"`` (w proportional to 1/distance, the
+    default), ``"gaussian"``, or an explicit (face, edge, corner) tuple; the
+    library fills in the named kinds (``nr_prior_init``)."""
     p: float = 1.2
     sigma: float = 1.0 / 0.7
     c: float = 1e-4
     lam: float = 1.0
-    weights: tuple = field(default_factory=_inverse_distance_weights)
+    weights: object = "inv_distance"
 
     def as_c(self) -> NrPrior:
+        if isinstance(self.weights, str):
+            if self.weights not in _WEIGHT_KINDS:
+                raise ValueError(f"weights must be one of {sorted(_WEIGHT_KINDS)} or a (face, edge, corner) tuple")
+            out = NrPrior()
+            check(lib().nr_prior_init(ctypes.byref(out), self.p, self.sigma, self.c, self.lam,
+                                      _WEIGHT_KINDS[self.weights]), "nr_prior_init")
+            return out
         wf, we, wc = self.weights
         return NrPrior(self.p, self.sigma, self.c, self.lam, wf, we, wc)
 
     def lipschitz(self) -> float:
-        return 8.0 * self.lam / (self.c * self.sigma ** 2)
+        """A Lipschitz constant of the prior's gradient (``nr_prior_lipschitz``)."""
+        out = ctypes.c_double()
+        check(lib().nr_prior_lipschitz(ctypes.byref(self.as_c()), ctypes.byref(out)), "nr_prior_lipschitz")
+        return float(out.value)
 
 
 def qggmrf_grad(vol: torch.Tensor, prior: Prior, scale: float = 1.0, grad: torch.Tensor | None = None,
@@ -425,12 +516,18 @@ class QGGMRFFn(torch.autograd.Function):
 class MBIR:
     """Accelerated-gradient MBIR on the device: one ``mbir_step`` per iteration.
 
-    State ``{x, x_prev, y, grad, t}`` lives on the device; ``step()``
-    enqueues one iteration without synchronising the host.
+    State ``{x, x_prev, y, grad, t, ...}`` lives on the device; ``step()``
+    enqueues one iteration without synchronising the host.  The step size
+    is ``1/L``: ``L`` given whole, or ``L_data`` (the largest eigenvalue of
+    ``R^T R``) to which the library adds the prior's constant, or neither
+    (the library's power iteration).  ``restart``: the gradient restart test;
+    ``monotone``: reject a step that raises the objective (one more forward
+    projection per iteration).
     """
 
-    def __init__(self, plan: Plan, b: torch.Tensor, prior: Prior, L: float, nonneg: bool = False,
-                 x0: torch.Tensor | None = None):
+    def __init__(self, plan: Plan, b: torch.Tensor, prior: Prior, L: float | None = None,
+                 nonneg: bool = False, x0: torch.Tensor | None = None, L_data: float | None = None,
+                 restart: bool = True, monotone: bool = False):
         if not plan.uniform:
             raise ValueError("MBIR needs a uniform stack (one N for every slice)")
         self.plan, self.b, self.prior = plan, b.contiguous(), prior
@@ -442,10 +539,18 @@ class MBIR:
         self.x_prev = self.x.clone()
         self.grad = torch.zeros_like(self.x)
         self.scratch = torch.empty(plan.sino_shape(), dtype=torch.float32, device=dev)
-        self.state = torch.zeros(8, dtype=torch.float64, device=dev)
-        self.state[0] = 1.0
-        self.params = NrMbir(1.0 / float(L), 1 if nonneg else 0)
+        self.state = torch.empty(NR_MBIR_STATE_DOUBLES, dtype=torch.float64, device=dev)
+        with torch.cuda.device(dev):
+            check(lib().mbir_state_init(_ptr(self.state), _stream(dev)), "mbir_state_init")
         self._prior_c = prior.as_c()
+        self.params = NrMbir()
+        flags = (1 if restart else 0, 1 if nonneg else 0, 1 if monotone else 0)
+        if L is not None:
+            check(lib().nr_mbir_params(float(L), None, *flags, ctypes.byref(self.params)), "nr_mbir_params")
+        else:
+            ld = power_lipschitz(plan) if L_data is None else float(L_data)
+            check(lib().nr_mbir_params(ld, ctypes.byref(self._prior_c), *flags, ctypes.byref(self.params)),
+                  "nr_mbir_params")
         self.k = 0
 
     def step(self) -> None:
@@ -495,6 +600,17 @@ class MBIR:
     def nonfinite(self) -> bool:
         return bool(self.state[2].item() != 0.0)
 
+    @property
+    def rejected(self) -> int:
+        """Steps the monotone test rejected so far."""
+        return int(self.state[10].item())
+
+    @property
+    def objective(self) -> float:
+        """Objective at x recorded by the last monotone step (NaN before one ran)."""
+        st = self.state[5:7].cpu()
+        return float(st[0]) if float(st[1]) != 0.0 else float("nan")
+
 
 def stream_stack(what: str, host_in: torch.Tensor, n: int, n_det: int, angles, chunk: int, center: float = 0.0,
                  device: torch.device | str | None = None, filter: str = "ramp", order: int = 2,
@@ -526,16 +642,18 @@ def stream_stack(what: str, host_in: torch.Tensor, n: int, n_det: int, angles, c
 
 
 def power_lipschitz(plan: Plan, iters: int = 30, seed: int = 0, safety: float = 1.01) -> float:
-    """Largest eigenvalue of ``R^T R`` for the plan (power iteration, times ``safety``)."""
-    gen = torch.Generator(device=plan.device).manual_seed(seed)
-    v = torch.randn(plan.vol_shape(), generator=gen, device=plan.device, dtype=torch.float32)
-    v /= torch.linalg.vector_norm(v)
-    lam = 0.0
-    for _ in range(iters):
-        w = plan.adj(plan.fwd(v))
-        lam = float(torch.linalg.vector_norm(w.double()))
-        v = (w / lam).contiguous()
-    return safety * lam
+    """Largest eigenvalue of ``R^T R`` for the plan, times ``safety``
+    (``nr_power_lipschitz``: power iteration on the device, float64 norms)."""
+    dev = plan.device
+    v = torch.empty(plan.vol_numel, dtype=torch.float32, device=dev)
+    w = torch.empty_like(v)
+    s = torch.empty(plan.sino_numel, dtype=torch.float32, device=dev)
+    work = torch.empty(1, dtype=torch.float64, device=dev)
+    out = ctypes.c_double()
+    with torch.cuda.device(dev):
+        check(lib().nr_power_lipschitz(plan._h, int(iters), int(seed) & (2 ** 64 - 1), float(safety), _ptr(v), _ptr(w),
+                                       _ptr(s), _ptr(work), ctypes.byref(out), _stream(dev)), "nr_power_lipschitz")
+    return float(out.value)
 
 
 def kb_eval(width: int, beta: float, u: np.ndarray, xi: np.ndarray):

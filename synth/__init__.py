@@ -21,6 +21,7 @@ from .phantoms import (  # noqa: F401
     uniform_angles,
     sparse_angles,
     limited_view_angles,
+    uneven_stack,
     poisson_log_data,
     gaussian_noise,
 )

@@ -270,6 +270,20 @@ def limited_view_angles(rng: np.random.Generator, n_angles: int) -> np.ndarray:
     return uniform_angles(n_angles, span, off)
 
 
+def uneven_stack(rng: np.random.Generator, count: int, sizes=(512, 1024, 2048),
+                 angle_range=(128, 1500)) -> list[tuple[int, np.ndarray]]:
+    """``count`` slices of an uneven stack: (N, angles) with N drawn from
+    ``sizes``, the angle count uniform in ``angle_range`` (inclusive), even
+    slices sparse (span pi, random offset) and odd ones limited-view."""
+    out = []
+    for i in range(count):
+        n = int(rng.choice(list(sizes)))
+        na = int(rng.integers(angle_range[0], angle_range[1] + 1))
+        ang = sparse_angles(rng, na) if i % 2 == 0 else limited_view_angles(rng, na)
+        out.append((n, ang))
+    return out
+
+
 # --------------------------------------------------------------------------
 # measurement noise (takes the clean data as input)
 # --------------------------------------------------------------------------

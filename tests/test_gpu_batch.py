@@ -147,9 +147,15 @@ def test_autotuner_picks_a_setting_and_caches_it(dev, tmp_path):
     say("case: autotuner on an uneven stack of 6")
     geoms = uneven_geoms(66, 6)
     cache = str(tmp_path / "tune.json")
-    best = autotune(geoms, device=dev, reps=1, cache_path=cache)
-    assert set(best) >= {"tile_w", "tile_h", "chunk", "batch_mb"}
-    assert autotune(geoms, device=dev, reps=1, cache_path=cache) == best      # served from the cache
+    best = autotune(geoms, device=dev, cache_path=cache)
+    assert set(best) >= {"tile_w", "tile_h", "chunk", "batch_mb", "streams"}
+    text = open(cache).read()
+    assert '"tile_w"' in text and '"ms"' in text
+    assert autotune(geoms, device=dev, cache_path=cache) == best      # served from the cache
+    # the library's own record: a timed search, then a cache hit with no trials
+    with Plan(geoms, device=dev) as p2:
+        p2.autotune(cache)
+        assert p2.get_tune("autotune_trials") == 0
     rng = np.random.default_rng(67)
     ref = Plan(geoms, device=dev)
     tuned = Plan(geoms, device=dev, tuning=best)

@@ -1,11 +1,15 @@
 """Parity at the benchmark's full size: 2560 x 2560 slices, 1024 angles, 2560 bins.
 
 The FP64 oracle is evaluated on sampled angles (its cost is linear in the
-angle count); properties that hold at any size (mass conservation per
-angle) are checked on every angle.
+angle count) or on sampled pixels (the closed form costs N_theta N_t per
+pixel); properties that hold at any size (mass conservation per angle) are
+checked on every angle.  The dense adjoint cases put data on every angle,
+so the cells around the spectrum's origin receive the low frequencies of all
+1024 angles (the spreading's heaviest tiles).
 """
 
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -13,11 +17,36 @@ import torch
 
 import synth
 from oracle import radon as ora
+from tests.analytic import ellipse_projection
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
 N, NA = 2560, 1024
-SAMPLE = np.array([0, 341, 682, 1023])
+SAMPLE = np.arange(0, NA, 64)          # 16 angles: a = 0, 64, ..., 960
+
+
+def adj_entries(y, ang, n, pixels):
+    """oracle.radon_adj_entries over chunks of pixels on host threads (numpy
+    releases the GIL inside its array operations)."""
+    chunks = [pixels[i::16] for i in range(16)]
+    with ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda c: ora.radon_adj_entries(y, ang, n, c), chunks))
+    out = np.empty(len(pixels))
+    for i, part in enumerate(parts):
+        out[i::16] = part
+    return out
+
+
+def sample_pixels(seed, n, block):
+    """A block x block square at the centre and 48 pixels drawn over the inscribed disc."""
+    c = n // 2
+    px = [(c - block // 2 + i, c - block // 2 + j) for i in range(block) for j in range(block)]
+    rng = np.random.default_rng(seed)
+    while len(px) < block * block + 48:
+        iy, ix = rng.integers(0, n, 2)
+        if (iy - c) ** 2 + (ix - c) ** 2 < (0.45 * n) ** 2:
+            px.append((int(iy), int(ix)))
+    return px
 
 
 def rel(a, b):
@@ -60,6 +89,29 @@ def test_adjoint_sampled_angles(setup):
     e = rel(g, ref)
     print(f"adj rel L2 (y on {len(SAMPLE)} angles): {e:.3e}", flush=True)
     assert e < TOL
+
+
+@pytest.mark.parametrize("kind", ["ellipse projections", "random"])
+def test_adjoint_dense_sampled_pixels(setup, kind):
+    """Adjoint of data on all 1024 angles: the analytic projections of an
+    ellipse phantom (non-negative, dominated by low frequencies) and white
+    noise, against the closed form on a 16 x 16 block at the centre and 48
+    pixels over the disc."""
+    dev, ang, f, plan = setup
+    print(f"case: dense adjoint, {kind}, 2560^2, 1024 angles", flush=True)
+    if kind == "random":
+        y = np.random.default_rng(11).standard_normal((NA, N))
+    else:
+        params = synth.ellipse_params(synth.rng_for(2, 5), N, 20)
+        y = ellipse_projection(params, ang, ora.pixel_coords(N))
+    g = plan.adj(torch.as_tensor(y[None], dtype=torch.float32, device=dev)).cpu().numpy()[0]
+    px = sample_pixels(12, N, 16)
+    ref = adj_entries(y, ang, N, px)
+    got = np.array([g[iy, ix] for iy, ix in px])
+    e = rel(got, ref)
+    e_c = rel(got[:256], ref[:256])
+    print(f"dense adj rel L2 ({kind}): {e:.3e} on {len(px)} pixels, centre block {e_c:.3e}", flush=True)
+    assert e < TOL and e_c < TOL
 
 
 def test_2048_forward_and_adjoint_sampled():

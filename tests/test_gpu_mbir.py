@@ -150,3 +150,50 @@ def test_nonfinite_data_sets_the_flag(dev):
     m = MBIR(plan, b, Prior(lam=0.0), 100.0)
     m.step()
     assert m.nonfinite
+
+
+@pytest.mark.parametrize("restart,monotone,frac", [(True, True, 1.0), (False, False, 1.0), (True, True, 0.8)])
+def test_mbir_step_flags_match_oracle_iterates(dev, restart, monotone, frac):
+    """mbir_step with the restart test on or off and the monotone rejection
+    test, against the oracle's iterates; frac < 1 takes a step longer than
+    1/L so that the monotone test rejects some steps."""
+    from paper_2304_12934_amd import MBIR, Plan, Prior
+    say(f"case: mbir_step restart={restart} monotone={monotone} L x {frac}")
+    rng = np.random.default_rng(42)
+    n, nz, na = 32, 3, 48
+    vol = synth.rasterize_ellipsoids(synth.ellipsoid_params(rng, n, nz, 4), n, nz).numpy()
+    ang = synth.uniform_angles(na)
+    A, At = omb.radon_ops(ang, n, n)
+    b = A(vol) + 0.01 * rng.standard_normal((nz, na, n))
+    oprior = omb.Prior(p=1.2, sigma=1.0, c=0.01, lam=0.5)
+    L = frac * (omb.power_lipschitz(A, At, vol.shape, iters=60) + oprior.lipschitz())
+    ref = omb.State(np.zeros(vol.shape), np.zeros(vol.shape))
+    plan = Plan.uniform_stack(n, n, ang, nz, device=dev)
+    m = MBIR(plan, gpu(b, dev), Prior(p=1.2, sigma=1.0, c=0.01, lam=0.5), L, restart=restart, monotone=monotone)
+    for k in range(12):
+        ref = omb.step(ref, b, A, At, oprior, L, restart=restart, monotone=monotone)
+        m.step()
+        assert rel(m.x.cpu().numpy(), ref.x) < 1e-5, k
+        assert abs(float(m.state[0].item()) - ref.t) < 1e-12, k
+        if monotone:
+            assert abs(m.objective - ref.phi) / ref.phi < 1e-5, k
+    assert m.restarts == ref.restarts and m.rejected == ref.rejected
+    say(f"restarts {m.restarts}, rejected {m.rejected}")
+
+
+def test_power_iteration_and_step_size_in_the_library(dev):
+    """nr_power_lipschitz against the largest singular value of the explicit
+    matrix (squared), and the step size of nr_mbir_params."""
+    from oracle import radon as ora
+    from paper_2304_12934_amd import MBIR, Plan, Prior, power_lipschitz
+    say("case: power iteration 2 x 16^2, 24 angles")
+    n, na = 16, 24
+    ang = synth.uniform_angles(na, offset=0.1)
+    top = np.linalg.svd(ora.radon_matrix(n, ang, n), compute_uv=False)[0] ** 2
+    plan = Plan.uniform_stack(n, n, ang, 2, device=dev)
+    lr = power_lipschitz(plan, iters=300, safety=1.0)
+    assert abs(lr - top) / top < 1e-5
+    assert abs(power_lipschitz(plan, iters=300, safety=1.25) / lr - 1.25) < 1e-6
+    prior = Prior(lam=0.3)
+    m = MBIR(plan, torch.zeros(plan.sino_shape(), device=dev), prior, L_data=lr)
+    assert abs(m.params.inv_L - 1.0 / (lr + omb.Prior(lam=0.3).lipschitz())) < 1e-6 * m.params.inv_L

@@ -157,3 +157,54 @@ def test_plan_info_and_workspace(L):
     assert L.nr_plan_tune(h, b"interp_mode", 1) == _lib.NR_OK
     assert L.nr_plan_info(h, 0, info, 8) == _lib.NR_OK and info[7] == 2 * (3 + 5)   # two batches
     L.nr_plan_destroy(h)
+
+
+def test_prior_weights_and_lipschitz_in_the_library(L):
+    """nr_prior_init's weights and nr_prior_lipschitz against the oracle's readings."""
+    from oracle import mbir as omb
+    from oracle import qggmrf as oq
+    from paper_2304_12934_amd import Prior
+    from paper_2304_12934_amd._lib import NrMbir, NrPrior
+    for kind, ref in (("inv_distance", oq.inverse_distance_weights()), ("gaussian", oq.gaussian_weights())):
+        c = Prior(p=1.2, sigma=1.0 / 0.7, c=1e-4, lam=0.7, weights=kind).as_c()
+        got = (c.w_face, c.w_edge, c.w_corner)
+        assert np.allclose(got, (ref[1], ref[2], ref[3]), rtol=1e-6, atol=0)
+    # float32 parameters: equal to float32 rounding
+    assert abs(Prior(lam=0.7).lipschitz() - omb.Prior(lam=0.7).lipschitz()) < 1e-6 * omb.Prior(lam=0.7).lipschitz()
+    with pytest.raises(ValueError):
+        Prior(weights="box").as_c()
+    out = NrMbir()
+    pr = Prior(lam=0.5, c=0.01, sigma=1.0).as_c()
+    assert L.nr_mbir_params(3.0, ctypes.byref(pr), 1, 0, 1, ctypes.byref(out)) == 0
+    assert abs(out.inv_L - 1.0 / (3.0 + 8 * 0.5 / 0.01)) < 1e-9 and out.restart == 1 and out.monotone == 1
+    assert L.nr_mbir_params(-1.0, None, 1, 0, 0, ctypes.byref(out)) != 0
+    assert L.nr_mbir_params(2.0, None, 1, 2, 0, ctypes.byref(out)) != 0      # flags are 0 or 1
+    bad = NrPrior(0.5, 1.0, 1e-4, 1.0, 0.1, 0.1, 0.1)                          # p < 1
+    v = ctypes.c_double()
+    assert L.nr_prior_lipschitz(ctypes.byref(bad), ctypes.byref(v)) != 0
+
+
+def test_autotune_scratch_and_tuning_keys(L):
+    """Host side of the autotuner: the scratch bound covers every candidate
+    layout, and the tuning keys read back."""
+    from paper_2304_12934_amd import _lib
+    ang = np.linspace(0, np.pi, 40, endpoint=False)
+    st, h = _create(L, [(128, 128, 40, 0, 0, 0), (64, 64, 40, 128 * 128, 40 * 128, 0)], ang)
+    assert st == _lib.NR_OK
+    need = ctypes.c_size_t()
+    assert L.nr_autotune_scratch_bytes(h, ctypes.byref(need)) == _lib.NR_OK
+    v = ctypes.c_int64()
+    for key, want in (("tile_w", 64), ("tile_h", 32), ("chunk", 1024), ("batch_mb", 160), ("streams", 2),
+                      ("autotune_us", -1), ("autotune_trials", 0)):
+        assert L.nr_plan_get_tune(h, key.encode(), ctypes.byref(v)) == _lib.NR_OK and v.value == want, key
+    assert L.nr_plan_get_tune(h, b"no_such_key", ctypes.byref(v)) == _lib.NR_INVALID_ARG
+    for mb in (1, 160, 640, 1400, 2048):
+        for ns in (1, 2, 3, 6):
+            for tw, th in ((64, 32), (32, 32), (64, 64), (128, 32)):
+                assert L.nr_plan_tune(h, b"batch_mb", mb) == 0 and L.nr_plan_tune(h, b"streams", ns) == 0
+                assert L.nr_plan_tune(h, b"tile_w", tw) == 0 and L.nr_plan_tune(h, b"tile_h", th) == 0
+                ws = ctypes.c_size_t()
+                assert L.nr_plan_workspace_bytes(h, ctypes.byref(ws)) == 0
+                assert ws.value + 2 * 4 * (128 * 128 + 64 * 64) + 4 * 40 * 192 <= need.value
+    # without a device the tuner itself stops at its first HIP call with a status, not a crash
+    L.nr_plan_destroy(h)

@@ -122,3 +122,72 @@ def test_gradient_fd_on_crop_geometry():
         e[idx] = h
         fd = (mbir.objective(x + e, b, A, prior) - mbir.objective(x - e, b, A, prior)) / (2 * h)
         assert abs(g[idx] - fd) <= 1e-7 * max(abs(fd), np.abs(g).max() * 1e-3)
+
+
+def _objectives(b, A, At, prior, L, iters, **kw):
+    vals = []
+    mbir.run(b, A, At, (NZ, N, N), prior, L, iters,
+             callback=lambda s: vals.append(mbir.objective(s.x, b, A, prior)), **kw)
+    return np.array(vals)
+
+
+def test_monotone_variant_never_rises_and_reaches_the_minimum():
+    """Sec. 3's optimiser keeps the objective from rising: with a valid step the
+    monotone variant's objective never increases and it reaches the same
+    minimum as an independent solver (L-BFGS)."""
+    ang, A, At, b = _data(26)
+    prior = mbir.Prior(p=1.2, sigma=1.0, c=0.05, lam=0.5)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=100) + prior.lipschitz()
+    vals = _objectives(b, A, At, prior, L, 600, monotone=True)
+    assert np.all(np.diff(vals) <= 0.0)
+    st = mbir.run(b, A, At, (NZ, N, N), prior, L, iters=2500, monotone=True)
+    phi = lambda v: mbir.objective(v.reshape(NZ, N, N), b, A, prior)            # noqa: E731
+    jac = lambda v: mbir.gradient(v.reshape(NZ, N, N), b, A, At, prior).ravel()  # noqa: E731
+    res = minimize(phi, np.zeros(NZ * N * N), jac=jac, method="L-BFGS-B",
+                   options={"maxiter": 20000, "ftol": 1e-15, "gtol": 1e-12, "maxcor": 30})
+    assert abs(phi(st.x.ravel()) - res.fun) / abs(res.fun) < 1e-6
+
+
+def test_monotone_test_catches_rising_steps():
+    """With a step longer than 1/L_R (L = 0.8 L_R) the momentum lets the
+    objective rise now and then; the monotone variant rejects those steps,
+    never rises, and still reaches the least-squares solution."""
+    ang, A, At, b = _data(27)
+    M = radon.radon_matrix(N, ang, ND)
+    ref = np.stack([np.linalg.lstsq(M, b[z].ravel(), rcond=None)[0].reshape(N, N) for z in range(NZ)])
+    L = 0.8 * mbir.power_lipschitz(A, At, (NZ, N, N), iters=200, safety=1.0)
+    plain = _objectives(b, A, At, None, L, 1500)
+    assert np.any(np.diff(plain) > 0.0)
+    mono = _objectives(b, A, At, None, L, 1500, monotone=True)
+    assert np.all(np.diff(mono) <= 0.0)
+    st = mbir.run(b, A, At, (NZ, N, N), None, L, iters=3000, monotone=True)
+    assert st.rejected > 0
+    assert np.linalg.norm(st.x - ref) / np.linalg.norm(ref) < 1e-6
+
+
+def test_rejected_step_keeps_x_and_restarts():
+    ang, A, At, b = _data(27)
+    L = 0.8 * mbir.power_lipschitz(A, At, (NZ, N, N), iters=200, safety=1.0)
+    st = mbir.State(np.zeros((NZ, N, N)), np.zeros((NZ, N, N)))
+    seen = 0
+    for _ in range(1500):
+        prev = st
+        st = mbir.step(st, b, A, At, None, L, monotone=True)
+        if st.rejected > prev.rejected:
+            seen += 1
+            assert np.array_equal(st.x, prev.x) and np.array_equal(st.y, st.x)
+            assert st.t == 0.5 * (1.0 + np.sqrt(5.0)) and st.phi == prev.phi
+        if seen == 2:
+            break
+    assert seen >= 1
+
+
+def test_restart_flag_off_is_plain_momentum():
+    """restart=False never resets t: t_k follows t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2 from t_0 = 1."""
+    ang, A, At, b = _data(29)
+    L = mbir.power_lipschitz(A, At, (NZ, N, N), iters=50)
+    st = mbir.run(b, A, At, (NZ, N, N), None, L, iters=40, restart=False)
+    t = 1.0
+    for _ in range(40):
+        t = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+    assert st.restarts == 0 and st.t == t

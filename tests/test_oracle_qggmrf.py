@@ -118,3 +118,16 @@ def test_planted_missing_factor_two_is_caught():
     e[1, 1, 1] = h
     fd = (qggmrf.value(f + e) - qggmrf.value(f - e)) / (2 * h)
     assert abs(bad[1, 1, 1] - fd) > 0.1 * abs(fd)
+
+
+def test_gaussian_weights_shape():
+    """The alternative weights are exp(-d^2/2) normalised over the 26 neighbours:
+    each step in squared distance divides the weight by e^{1/2}."""
+    w = qggmrf.gaussian_weights()
+    assert abs(w[1] / w[2] - np.exp(0.5)) < 1e-14 and abs(w[2] / w[3] - np.exp(0.5)) < 1e-14
+    assert abs(6 * w[1] + 12 * w[2] + 8 * w[3] - 1.0) < 1e-15
+    # the same Gaussian evaluated at each neighbour's offset, normalised by brute force
+    raw = {o: np.exp(-0.5 * sum(c * c for c in o)) for o in qggmrf.OFFSETS}
+    total = sum(raw.values())
+    for o, v in raw.items():
+        assert abs(w[sum(abs(c) for c in o)] - v / total) < 1e-15
