@@ -53,6 +53,10 @@ struct nr_plan {
   std::vector<hipEvent_t> lane_done;
   std::vector<hipEvent_t> lane_skew;
   hipEvent_t fork = nullptr;
+  // MBIR: the prior gradient runs on its own stream beside the projector
+  int side_device = -1;
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_done = nullptr;
   // host streaming: copy-in and copy-out streams and the events that order
   // the two chunk buffers between them and the compute stream
   int io_device = -1;
@@ -78,6 +82,12 @@ struct nr_plan {
     fork = nullptr;
     lane_device = -1;
   }
+  void drop_side() {
+    if (side) (void)hipStreamDestroy(side), side = nullptr;
+    for (hipEvent_t* e : {&side_fork, &side_done})
+      if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+    side_device = -1;
+  }
   ~nr_plan() {
     for (auto& r : recorded) {
       (void)hipEventDestroy(r.start);
@@ -86,6 +96,7 @@ struct nr_plan {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     drop_lanes();
     drop_io();
+    drop_side();
   }
 };
 
@@ -198,6 +209,20 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
   return hipSuccess;
 }
 
+// The plan's prior stream on the current device (created on first use).
+hipError_t ensure_side(nr_plan* plan) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (plan->side_device == dev && plan->side) return hipSuccess;
+  plan->drop_side();
+  plan->side_device = dev;
+  if ((e = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (hipEvent_t* ev : {&plan->side_fork, &plan->side_done})
+    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
 // Enqueue, for every batch, the forward chain (vol_in -> sino_out), then the
 // residual sino_out -= b of its slices (b not null), then the adjoint chain
 // (sino_in -> vol_out), as asked.  With several lanes the batches run
@@ -206,12 +231,11 @@ hipError_t ensure_lanes(nr_plan* plan, int n) {
 // forward on its lane, with no join in between.
 nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const float* vol_in, float* vol_out,
                       const float* sino_in, float* sino_out, hipStream_t st, const char* where,
-                      const nr_fbp* fbp = nullptr, const void* ws = nullptr) {
+                      const nr_fbp* fbp = nullptr) {
   const nr::Plan& p = plan->p;
   // while stages are being timed they run one at a time on st, so that each
-  // event pair times its stage alone; a workspace other than the bound one
-  // (the static one) is used from st alone too
-  const int nl = (plan->profiling || ws) ? 1 : p.n_lanes;
+  // event pair times its stage alone
+  const int nl = plan->profiling ? 1 : p.n_lanes;
   if (nl > 1) {
     hipError_t e = ensure_lanes(plan, nl);
     if (e == hipSuccess) e = hipEventRecord(plan->fork, st);
@@ -220,7 +244,7 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
   }
   auto lane_stream = [&](const nr::Batch& bt) { return nl > 1 ? plan->lanes[size_t(bt.lane)] : st; };
   const nrk::KBArgs kb = kb_args(p);
-  const char* base = static_cast<const char*>(ws ? ws : p.d_ws);
+  const char* base = static_cast<const char*>(p.d_ws);
   nrk::LaunchArgs a{};
   a.descs = reinterpret_cast<const SliceDesc*>(base + p.off_desc);
   a.halo = p.halo;
@@ -853,20 +877,42 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t count = size_t(nz) * n * n;
   const nrk::PriorArgs pa = prior_args(prior);
-  // R^T (R y - b) into d_grad, batch by batch
-  if (nr_status s = radon_normal(plan, d_y, d_b, d_scratch, d_grad, stream)) return s;
   hipError_t e = hipSuccess;
-  if (prior->lambda > 0.0f) {
-    e = timed(plan, kStagePrior, st, [&] { return nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, pa, 1.0f, st); });
-    if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
-  }
   if (!params->monotone) {
+    // The prior gradient (arithmetic-bound) runs beside the projector
+    // (memory-bound) on the plan's prior stream, into d_x_prev: the update
+    // overwrites d_x_prev without reading it, and adds it to d_grad first.
+    // While stages are timed, it runs on st before the projector instead.
+    const bool prior_on = prior->lambda > 0.0f;
+    const bool side = prior_on && !plan->profiling;
+    if (side) {
+      e = ensure_side(plan);
+      if (e == hipSuccess) e = hipEventRecord(plan->side_fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->side_fork, 0);
+      if (e == hipSuccess) e = nrk::launch_qggmrf(d_y, d_x_prev, nullptr, nz, n, pa, 1.0f, plan->side, false);
+      if (e == hipSuccess) e = hipEventRecord(plan->side_done, plan->side);
+      if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
+    } else if (prior_on) {
+      e = timed(plan, kStagePrior, st, [&] {
+        return nrk::launch_qggmrf(d_y, d_x_prev, nullptr, nz, n, pa, 1.0f, st, false);
+      });
+      if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
+    }
+    // R^T (R y - b) into d_grad, batch by batch
+    if (nr_status s = radon_normal(plan, d_y, d_b, d_scratch, d_grad, stream)) return s;
+    if (side && (e = hipStreamWaitEvent(st, plan->side_done, 0)) != hipSuccess) return hip_fail(e, "mbir_step join");
     e = timed(plan, kStageUpdate, st, [&] {
       return nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, count, params->inv_L, params->nonneg,
-                                     params->restart, d_state, st);
+                                     params->restart, d_state, st, prior_on);
     });
     if (e != hipSuccess) return hip_fail(e, "mbir_step update");
     return NR_OK;
+  }
+  // R^T (R y - b) into d_grad, batch by batch
+  if (nr_status s = radon_normal(plan, d_y, d_b, d_scratch, d_grad, stream)) return s;
+  if (prior->lambda > 0.0f) {
+    e = timed(plan, kStagePrior, st, [&] { return nrk::launch_qggmrf(d_y, d_grad, nullptr, nz, n, pa, 1.0f, st); });
+    if (e != hipSuccess) return hip_fail(e, "mbir_step prior");
   }
   // monotone: the candidate x' (into d_x_prev) and its objective
   e = timed(plan, kStageUpdate, st, [&] {
@@ -897,7 +943,8 @@ nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float*
   if (params->monotone)
     return fail(NR_INVALID_ARG, "mbir_update: the monotone step needs the objective (use mbir_step)");
   if (nr_status st = pending_error("before mbir_update")) return st;
-  const hipError_t e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, d_grad, size_t(count), params->inv_L,
+  const hipError_t e = nrk::launch_mbir_update(d_x, d_x_prev, d_y, const_cast<float*>(d_grad), size_t(count),
+                                               params->inv_L,
                                                params->nonneg, params->restart, d_state,
                                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mbir_update launch");

@@ -7,13 +7,18 @@
 //   dH/df_m = (2 lambda/sigma) sum_n w_mn rho'((f_m - f_n)/sigma)
 // (H sums rho over ordered pairs; each unordered pair appears twice.)
 //
-// The stencil kernel stages a block of the volume with a one-voxel halo in
-// LDS (the "shared memory caching" of the paper's Sec. 4.1, reorganised for
-// 64-wide wavefronts), evaluates every unordered neighbour pair once and
-// accumulates into the gradient in place (Sec. 4, gradients updated in place).
+// The stencil kernel gives each wavefront a strip of the volume, 64 columns
+// wide (62 owned, one halo column on each side) and TY rows high, and marches
+// it along z: a lane holds its column of the strip for two consecutive planes
+// in registers, exchanges x-neighbours with its adjacent lanes by DPP wave
+// shifts, evaluates every unordered neighbour pair once and accumulates into
+// the gradient in place (Sec. 4, gradients updated in place).  Nothing is
+// staged in LDS and no barrier is taken: the neighbourhood caching of the
+// paper's Sec. 4.1 lives in registers here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "prior_kernels.hpp"
 
@@ -21,177 +26,292 @@ namespace nrk {
 
 namespace {
 
-// Block of 64 x 8 x 8 voxels (x, y, z), 512 threads: thread (lx, ly) owns the
-// z-column of 8 voxels (one wavefront per x-row).  The block stages its voxels
-// with a one-voxel halo in F; staged index of block-local (x, y, z), each in
-// [-1, T], is (z+1)*FP + (y+1)*FX + (x+1).  The pair terms of one direction go
-// to R (same indexing, z in [-1, TZ)), double-buffered across directions.
-constexpr int TX = 64, TY = 8, TZ = 8;
-constexpr int NT = TX * TY;
-constexpr int FX = TX + 2, FY = TY + 2, FZ = TZ + 2;
-constexpr int FP = FX * FY;
-constexpr int RSZ = (TZ + 1) * FP;
+// Wavefront tiling: lane l covers column x0 - 1 + l; lanes 1..OWN own their
+// column, lanes 0 and 63 only supply the neighbours of the owned ones.  Rows
+// are held as index i = 0..TY+1 for y = y0 - 1 + i; rows 1..TY are owned.
+constexpr int OWN = 62;
+constexpr int TY = 8;
+constexpr int QG_WAVES = 4;     // wavefronts per workgroup (independent strips)
 
-__device__ __forceinline__ float pow_2mp(float a, float e) {   // a^e for a > 0
-  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(a));   // v_exp_f32, v_log_f32 (base 2)
+// lane l receives lane l - 1 (lane 0 receives 0) / lane l + 1 (lane 63 receives 0)
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
 }
-
-// w rho'(u) and, with VALUE, w rho(u).  s = |u|^(2-p) is taken as 0 at u = 0
-// (a select, no branch); both results are 0 there whatever s is.
-template <bool VALUE>
-__device__ __forceinline__ float rho_prime(float u, const PriorArgs& pr, float w, float& rho) {
-  const float a = fabsf(u);
-  const float s = a > 0.f ? pow_2mp(a, 2.f - pr.p) : 0.f;
-  const float inv = __builtin_amdgcn_rcpf(pr.c + s);
-  if (VALUE) rho = w * a * a * inv;
-  return w * u * fmaf(pr.p, s, 2.f * pr.c) * inv * inv;
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
 }
+__device__ __forceinline__ int from_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int from_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
 
-struct BlockCtx {
-  int x0, y0, z0, n, nz, lx, ly, tid;
-  float inv_sigma;
-  __device__ __forceinline__ bool inside(int bx, int by, int bz) const {   // block-local coordinates
-    const int x = x0 + bx, y = y0 + by, z = z0 + bz;
-    return x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < nz;
-  }
+// Per neighbour class (face, edge, corner) the gradient term of a pair with
+// difference d = f_m - f_n is
+//   scale (2 lambda / sigma) w rho'(d / sigma) = d (Ap s + A2c) / (c + s)^2,
+//   s = |d / sigma|^(2-p) = 2^((2-p) log2|d| + (2-p) log2(1/sigma)),
+// with A = scale 2 lambda w / sigma^2, Ap = A p, A2c = A 2c; and the value
+// term w rho(d / sigma) = w d^2 / (sigma^2 (c + s)).  At d = 0, log2 gives
+// -inf and s = 0 (p < 2); with p = 2, s = 1.
+struct QgConst {
+  float e, elog, c;       // 2 - p, (2 - p) log2(1/sigma), c
+  float ap[3], a2c[3];    // face, edge, corner
+  float w[3];
 };
 
-__device__ __forceinline__ constexpr int fidx(int bx, int by, int bz) { return (bz + 1) * FP + (by + 1) * FX + (bx + 1); }
-
-// r_d at block-local m = (bx, by, bz): w rho'((f_m - f_{m+d})/sigma), 0 when m
-// or m + d lies outside the volume.
-template <bool VALUE, bool INTERIOR, int DZ, int DY, int DX>
-__device__ __forceinline__ float pair_term(const BlockCtx& b, const float* F, float fm, float fn, int bx, int by,
-                                           int bz, const PriorArgs& pr, float w, float& rho) {
-  if (!INTERIOR && !(b.inside(bx, by, bz) && b.inside(bx + DX, by + DY, bz + DZ))) {
-    rho = 0.f;
-    return 0.f;
-  }
-  return rho_prime<VALUE>((fm - fn) * b.inv_sigma, pr, w, rho);
+template <bool P2>
+__device__ __forceinline__ float qg_s(float d, const QgConst& k) {
+  if (P2) return 1.f;
+  return __builtin_amdgcn_exp2f(fmaf(k.e, __builtin_amdgcn_logf(fabsf(d)), k.elog));
 }
 
-// One of the 13 lexicographically positive offsets d = (DZ, DY, DX).  Each
-// unordered pair (m, m + d) is evaluated once: r_d(m) enters voxel m with +
-// and voxel m + d with - (rho' is odd), so voxel m gathers r_d(m) - r_d(m - d).
-// The terms r_d(m - d) of the block's own voxels come from the thread that owns
-// column m - d or, off the block, from the halo rows evaluated here.
-template <bool VALUE, bool INTERIOR, int DZ, int DY, int DX>
-__device__ __forceinline__ void direction(const BlockCtx& b, const float* F, float* R, const float (&fc)[FZ],
-                                          float (&acc)[TZ], float& hsum, const PriorArgs& pr) {
-  constexpr int d2 = DZ * DZ + DY * DY + DX * DX;
-  const float w = d2 == 1 ? pr.w_face : (d2 == 2 ? pr.w_edge : pr.w_corner);
-  constexpr int ZLO = -DZ;
-  float r[TZ + 1];   // r[z + 1] for z in [ZLO, TZ)
+// gradient term of one pair; with VALUE, h += w d^2/(c + s) (the value term
+// up to the factor 1/sigma^2 applied once at the end)
+template <bool VALUE, bool P2, int CLS>
+__device__ __forceinline__ float qg_term(float d, const QgConst& k, float& h) {
+  const float s = qg_s<P2>(d, k);
+  const float inv = __builtin_amdgcn_rcpf(k.c + s);
+  if (VALUE) h = fmaf(k.w[CLS] * d * d, inv, h);
+  return d * fmaf(k.ap[CLS], s, k.a2c[CLS]) * inv * inv;
+}
+
+// One wavefront's strip: columns x0-1 .. x0+62, rows y0-1 .. y0+TY, owned
+// planes [z0, z1).  EDGE: some column or row of the strip lies outside the
+// volume (pairs with a partner outside are dropped).
+template <bool VALUE, bool P2, bool EDGE, bool ACC>
+__device__ __forceinline__ void qg_strip(const float* __restrict__ f, float* __restrict__ grad, int n, int nz,
+                                         int x0, int y0, int z0, int z1, const QgConst& k, int lane,
+                                         double& hsum) {
+  const size_t plane = size_t(n) * n;
+  const int x = x0 - 1 + lane;
+  const bool lv = !EDGE || (x >= 0 && x < n);
+  // pairs with the right (x + 1) / left (x - 1) neighbour lie inside the volume
+  const bool okR = !EDGE || (lv && from_right_i(int(lv)) != 0);
+  const bool okL = !EDGE || (lv && from_left_i(int(lv)) != 0);
+  const bool own = lane >= 1 && lane <= OWN && x < n;
+  const int xc = EDGE ? min(max(x, 0), n - 1) : x;
+  // rows inside the volume (wave-uniform)
+  bool rv[TY + 2];
 #pragma unroll
-  for (int z = ZLO; z < TZ; ++z) {
-    const float fn = (DX == 0 && DY == 0) ? fc[z + 1 + DZ] : F[fidx(b.lx + DX, b.ly + DY, z + DZ)];
-    float rho;
-    r[z + 1] = pair_term<VALUE, INTERIOR, DZ, DY, DX>(b, F, fc[z + 1], fn, b.lx, b.ly, z, pr, w, rho);
-    if (VALUE && z >= 0) hsum += 2.f * rho;
+  for (int i = 0; i < TY + 2; ++i) rv[i] = !EDGE || (y0 - 1 + i >= 0 && y0 - 1 + i < n);
+  int roff[TY + 2];
+#pragma unroll
+  for (int i = 0; i < TY + 2; ++i) {
+    const int y = EDGE ? min(max(y0 - 1 + i, 0), n - 1) : y0 - 1 + i;
+    roff[i] = y * n + xc;
   }
-  if constexpr (DX == 0 && DY == 0) {   // d = (1, 0, 0): the partner term is in this thread
+
+  float p[TY + 2], q[TY + 2];
+  float accP[TY + 2], accQ[TY + 2], toR[TY + 2], toL[TY + 2];
+  float hP = 0.f, hQ = 0.f;   // value terms whose + side is in plane P / Q
+
+  const int zs = z0 > 0 ? z0 - 1 : 0;
+  const int zl = min(z1, nz - 1);
+
+  auto load_plane = [&](int z, float (&v)[TY + 2]) {
+    const float* fp = f + size_t(z) * plane;
 #pragma unroll
-    for (int z = 0; z < TZ; ++z) acc[z] += r[z + 1] - r[z];
-    return;
-  } else {
+    for (int i = 0; i < TY + 2; ++i) v[i] = fp[roff[i]];
+  };
+  // Materialise the accumulators between groups of pairs: otherwise the
+  // scheduler interleaves the transcendental chains of every pair of the
+  // z-step and runs out of registers.
+  auto fence = [&]() {
 #pragma unroll
-    for (int z = ZLO; z < TZ; ++z) R[fidx(b.lx, b.ly, z)] = r[z + 1];
-    float rho;
-    if constexpr (DY != 0) {   // the row y = -1 (DY > 0) or y = TY (DY < 0) of m - d: one term per thread
-      constexpr int yh = DY > 0 ? -1 : TY;
-      const int xh = (b.tid & (TX - 1)) - DX, zh = (b.tid / TX) - DZ;
-      R[fidx(xh, yh, zh)] = pair_term<false, INTERIOR, DZ, DY, DX>(
-          b, F, F[fidx(xh, yh, zh)], F[fidx(xh + DX, yh + DY, zh + DZ)], xh, yh, zh, pr, w, rho);
+    for (int i = 1; i <= TY; ++i) asm volatile("" : "+v"(accQ[i]), "+v"(accP[i]), "+v"(toR[i]), "+v"(toL[i]));
+  };
+  // a pair with a partner outside the volume contributes nothing
+  auto mask = [&](bool ok, float& r, float& h) {
+    if (EDGE) {
+      r = ok ? r : 0.f;
+      h = ok ? h : 0.f;
     }
-    if constexpr (DX != 0) {   // the column x = -1 (DX > 0) or x = TX (DX < 0): 64 terms, first wavefront
-      constexpr int xh = DX > 0 ? -1 : TX;
-      if (b.tid < TY * TZ) {
-        const int yh = (b.tid % TY) - DY, zh = (b.tid / TY) - DZ;
-        R[fidx(xh, yh, zh)] = pair_term<false, INTERIOR, DZ, DY, DX>(
-            b, F, F[fidx(xh, yh, zh)], F[fidx(xh + DX, yh + DY, zh + DZ)], xh, yh, zh, pr, w, rho);
+  };
+  // in-plane pairs of Q: (0,0,1), (0,1,0), (0,1,1), (0,1,-1)
+  auto in_plane = [&]() {
+#pragma unroll
+    for (int i = 1; i <= TY; ++i) {
+      if (!rv[i]) continue;
+      float h = 0.f;
+      float r = qg_term<VALUE, P2, 0>(q[i] - from_right(q[i]), k, h);
+      mask(okR, r, h);
+      accQ[i] += r;
+      if (VALUE) hQ += h;
+      toR[i] -= r;
+    }
+    fence();
+#pragma unroll
+    for (int i = 0; i <= TY; ++i) {
+      if (!(rv[i] && rv[i + 1])) continue;
+      float h = 0.f;
+      const float r = qg_term<VALUE, P2, 0>(q[i] - q[i + 1], k, h);
+      if (i >= 1) {
+        accQ[i] += r;
+        if (VALUE) hQ += h;
+      }
+      if (i + 1 <= TY) accQ[i + 1] -= r;
+    }
+    fence();
+#pragma unroll
+    for (int i = 0; i <= TY; ++i) {
+      if (!(rv[i] && rv[i + 1])) continue;
+      float h = 0.f;
+      float r = qg_term<VALUE, P2, 1>(q[i] - from_right(q[i + 1]), k, h);
+      mask(okR, r, h);
+      if (i >= 1) {
+        accQ[i] += r;
+        if (VALUE) hQ += h;
+      }
+      if (i + 1 <= TY) toR[i + 1] -= r;
+    }
+    fence();
+#pragma unroll
+    for (int i = 0; i <= TY; ++i) {
+      if (!(rv[i] && rv[i + 1])) continue;
+      float h = 0.f;
+      float r = qg_term<VALUE, P2, 1>(q[i] - from_left(q[i + 1]), k, h);
+      mask(okL, r, h);
+      if (i >= 1) {
+        accQ[i] += r;
+        if (VALUE) hQ += h;
+      }
+      if (i + 1 <= TY) toL[i + 1] -= r;
+    }
+  };
+  // pairs between P (plane z-1) and Q (plane z): d = (1, dy, dx)
+  auto cross = [&]() {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+      for (int i = 0; i <= TY + 1; ++i) {
+        const int j = i + dy;                            // row of the partner in Q
+        if (j < 0 || j > TY + 1) continue;
+        if ((i < 1 || i > TY) && (j < 1 || j > TY)) continue;   // neither side owned
+        if (!(rv[i] && rv[j])) continue;
+        // dx = 0
+        {
+          float h = 0.f;
+          const float r = dy == 0 ? qg_term<VALUE, P2, 0>(p[i] - q[j], k, h) : qg_term<VALUE, P2, 1>(p[i] - q[j], k, h);
+          if (i >= 1 && i <= TY) {
+            accP[i] += r;
+            if (VALUE) hP += h;
+          }
+          if (j >= 1 && j <= TY) accQ[j] -= r;
+        }
+        // dx = +1
+        {
+          float h = 0.f;
+          float r = dy == 0 ? qg_term<VALUE, P2, 1>(p[i] - from_right(q[j]), k, h) : qg_term<VALUE, P2, 2>(p[i] - from_right(q[j]), k, h);
+          mask(okR, r, h);
+          if (i >= 1 && i <= TY) {
+            accP[i] += r;
+            if (VALUE) hP += h;
+          }
+          if (j >= 1 && j <= TY) toR[j] -= r;
+        }
+        // dx = -1
+        {
+          float h = 0.f;
+          float r = dy == 0 ? qg_term<VALUE, P2, 1>(p[i] - from_left(q[j]), k, h) : qg_term<VALUE, P2, 2>(p[i] - from_left(q[j]), k, h);
+          mask(okL, r, h);
+          if (i >= 1 && i <= TY) {
+            accP[i] += r;
+            if (VALUE) hP += h;
+          }
+          if (j >= 1 && j <= TY) toL[j] -= r;
+        }
+        fence();
       }
     }
-    __syncthreads();
+  };
+  auto clear_q = [&]() {
 #pragma unroll
-    for (int z = 0; z < TZ; ++z) acc[z] += R[fidx(b.lx, b.ly, z)] - R[fidx(b.lx - DX, b.ly - DY, z - DZ)];
+    for (int i = 0; i < TY + 2; ++i) accQ[i] = 0.f, toR[i] = 0.f, toL[i] = 0.f;
+    hQ = 0.f;
+  };
+  // the terms this lane computed for its neighbours' columns
+  auto receive = [&]() {
+#pragma unroll
+    for (int i = 1; i <= TY; ++i) accQ[i] += from_left(toR[i]) + from_right(toL[i]);
+  };
+  auto write = [&](int z, const float (&acc)[TY + 2], float h) {
+    if (grad && own) {
+      float* gp = grad + size_t(z) * plane;
+#pragma unroll
+      for (int i = 1; i <= TY; ++i)
+        if (!EDGE || y0 - 1 + i < n) gp[roff[i]] = ACC ? gp[roff[i]] + acc[i] : acc[i];
+    }
+    if (VALUE && own) hsum += double(h);
+  };
+
+  // first plane: the owned plane z0 = 0, or the halo plane z0 - 1
+  load_plane(zs, q);
+  clear_q();
+  if (zs == z0) in_plane();
+  receive();
+  float qn[TY + 2];
+  for (int z = zs + 1; z <= zl; ++z) {
+#pragma unroll
+    for (int i = 0; i < TY + 2; ++i) p[i] = q[i], accP[i] = accQ[i];
+    hP = hQ;
+    load_plane(z, qn);
+#pragma unroll
+    for (int i = 0; i < TY + 2; ++i) q[i] = qn[i];
+      clear_q();
+    cross();
+    if (z < z1) in_plane();
+    receive();
+    if (z - 1 >= z0) write(z - 1, accP, hP);
   }
-  // Materialise the sums here: otherwise the compiler sinks every direction's
-  // adds into the guarded store at the end and keeps all loaded terms live.
-#pragma unroll
-  for (int z = 0; z < TZ; ++z) asm volatile("" : "+v"(acc[z]));
-  if (VALUE) asm volatile("" : "+v"(hsum));
+  if (zl < z1) write(zl, accQ, hQ);   // the volume's last plane is owned
 }
 
 }  // namespace
 
-template <bool VALUE, bool INTERIOR>
-__device__ __forceinline__ void qggmrf_block(const float* __restrict__ f, float* __restrict__ grad,
-                                             double* __restrict__ value, const BlockCtx& b, const PriorArgs& pr,
-                                             float scale, float* F, float* R0, float* R1, double* red) {
-  const size_t plane = size_t(b.n) * b.n;
-  for (int i = b.tid; i < FZ * FP; i += NT) {
-    const int bx = i % FX - 1, by = (i / FX) % FY - 1, bz = i / FP - 1;
-    float v = 0.f;
-    if (INTERIOR || b.inside(bx, by, bz)) v = f[size_t(b.z0 + bz) * plane + size_t(b.y0 + by) * b.n + (b.x0 + bx)];
-    F[i] = v;
-  }
-  __syncthreads();
-  float fc[FZ];
-#pragma unroll
-  for (int k = 0; k < FZ; ++k) fc[k] = F[fidx(b.lx, b.ly, k - 1)];
-  float acc[TZ];
-#pragma unroll
-  for (int z = 0; z < TZ; ++z) acc[z] = 0.f;
-  float hsum = 0.f;
-  // R buffers alternate between the directions that exchange terms through LDS,
-  // so one barrier per direction suffices.
-  direction<VALUE, INTERIOR, 1, 0, 0>(b, F, nullptr, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 0, 0, 1>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 0, 1, -1>(b, F, R1, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 0, 1, 0>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 0, 1, 1>(b, F, R1, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, -1, -1>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, -1, 0>(b, F, R1, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, -1, 1>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, 0, -1>(b, F, R1, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, 0, 1>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, 1, -1>(b, F, R1, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, 1, 0>(b, F, R0, fc, acc, hsum, pr);
-  direction<VALUE, INTERIOR, 1, 1, 1>(b, F, R1, fc, acc, hsum, pr);
-  const float gscale = scale * 2.f * pr.lambda * b.inv_sigma;
-  const int x = b.x0 + b.lx, y = b.y0 + b.ly;
-  if (grad && x < b.n && y < b.n) {   // no gradient output: the value alone
-#pragma unroll
-    for (int z = 0; z < TZ; ++z)
-      if (b.z0 + z < b.nz) grad[size_t(b.z0 + z) * plane + size_t(y) * b.n + x] += gscale * acc[z];
+// One workgroup = QG_WAVES independent wavefronts; wavefront g covers x-tile
+// g % xt, row strip (g / xt) % yt, z-chunk g / (xt yt).
+template <bool VALUE, bool P2, bool ACC>
+__device__ __forceinline__ void qggmrf_body(const float* __restrict__ f, float* __restrict__ grad,
+                                            double* __restrict__ value, int nz, int n, const QgConst& k, int xt,
+                                            int yt, int zchunk, int nwaves, double value_scale) {
+  __shared__ double red[QG_WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wave-uniform: keeps the strip's geometry and row tests in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * QG_WAVES + wv);
+  double hsum = 0.0;
+  if (g < nwaves) {
+    const int tx = g % xt, ty = (g / xt) % yt, tz = g / (xt * yt);
+    const int x0 = tx * OWN, y0 = ty * TY, z0 = tz * zchunk, z1 = min(nz, z0 + zchunk);
+    const bool interior = x0 >= 1 && x0 + OWN <= n - 1 && y0 >= 1 && y0 + TY <= n - 1;
+    if (interior) qg_strip<VALUE, P2, false, ACC>(f, grad, n, nz, x0, y0, z0, z1, k, lane, hsum);
+    else qg_strip<VALUE, P2, true, ACC>(f, grad, n, nz, x0, y0, z0, z1, k, lane, hsum);
   }
   if (VALUE) {
-    red[b.tid] = double(hsum);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
+    if (lane == 0) red[wv] = hsum;
     __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-      if (b.tid < w) red[b.tid] += red[b.tid + w];
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < QG_WAVES; ++w) t += red[w];
+      atomicAdd(value, value_scale * t);
     }
-    if (b.tid == 0) atomicAdd(value, double(pr.lambda) * red[0]);
   }
 }
 
-template <bool VALUE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_qggmrf(const float* __restrict__ f, float* __restrict__ grad,
-                                               double* __restrict__ value, int nz, int n, PriorArgs pr,
-                                               float scale) {
-  __shared__ float F[FZ * FP];
-  __shared__ float R0[RSZ], R1[RSZ];
-  __shared__ double red[VALUE ? NT : 1];
-  BlockCtx b;
-  b.x0 = blockIdx.x * TX, b.y0 = blockIdx.y * TY, b.z0 = blockIdx.z * TZ;
-  b.n = n, b.nz = nz, b.tid = threadIdx.x, b.lx = threadIdx.x % TX, b.ly = threadIdx.x / TX;
-  b.inv_sigma = 1.f / pr.sigma;
-  // interior block: the block and its halo lie inside the volume
-  const bool interior =
-      b.x0 >= 1 && b.x0 + TX + 1 <= n && b.y0 >= 1 && b.y0 + TY + 1 <= n && b.z0 >= 1 && b.z0 + TZ + 1 <= nz;
-  if (interior) qggmrf_block<VALUE, true>(f, grad, value, b, pr, scale, F, R0, R1, red);
-  else qggmrf_block<VALUE, false>(f, grad, value, b, pr, scale, F, R0, R1, red);
+// gradient only (ACC: added into grad, else stored): 4 wavefronts per SIMD
+// (the strip's registers fit in 128)
+template <bool P2, bool ACC>
+__global__ __launch_bounds__(64 * QG_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_qggmrf(
+    const float* __restrict__ f, float* __restrict__ grad, int nz, int n, QgConst k, int xt, int yt, int zchunk,
+    int nwaves) {
+  qggmrf_body<false, P2, ACC>(f, grad, nullptr, nz, n, k, xt, yt, zchunk, nwaves, 0.0);
+}
+
+// with the value: the extra accumulations need more registers
+template <bool P2>
+__global__ __launch_bounds__(64 * QG_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_qggmrf_value(
+    const float* __restrict__ f, float* __restrict__ grad, double* __restrict__ value, int nz, int n, QgConst k,
+    int xt, int yt, int zchunk, int nwaves, double value_scale) {
+  qggmrf_body<true, P2, true>(f, grad, value, nz, n, k, xt, yt, zchunk, nwaves, value_scale);
 }
 
 __global__ void k_set_double(double* p, double v) { *p = v; }
@@ -222,10 +342,13 @@ __global__ __launch_bounds__(256) void k_residual_norm(float* __restrict__ s, co
 }
 
 // <g, x' - x> with x' = y - g/L (clamped at 0 when nonneg); non-finite flag.
-// With cand, x' is also stored there (the monotone step evaluates it).
+// With cand, x' is also stored there (the monotone step evaluates it).  With
+// gp, the gradient is g + gp (a second part computed elsewhere), stored back
+// into g.
 __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, const float* __restrict__ y,
-                                                  const float* __restrict__ g, size_t count, float inv_L,
-                                                  int nonneg, double* state, float* __restrict__ cand) {
+                                                  float* __restrict__ g, size_t count, float inv_L,
+                                                  int nonneg, double* state, float* __restrict__ cand,
+                                                  const float* __restrict__ gp) {
   __shared__ double red[256];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -233,7 +356,11 @@ __global__ __launch_bounds__(256) void k_mbir_dot(const float* __restrict__ x, c
   double acc = 0.0;
   int nf = 0;
   for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
-    const float gi = g[i];
+    float gi = g[i];
+    if (gp) {
+      gi += gp[i];
+      g[i] = gi;
+    }
     float xn = y[i] - inv_L * gi;
     if (nonneg) xn = fmaxf(xn, 0.f);
     acc += double(gi) * double(xn - x[i]);
@@ -366,11 +493,45 @@ __global__ __launch_bounds__(256) void k_scale_inv_norm(float* __restrict__ v, c
 }
 
 hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int n, const PriorArgs& pr,
-                         float scale, hipStream_t st) {
+                         float scale, hipStream_t st, bool accumulate) {
   if (value) hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, value, 0.0);
-  const dim3 grid((n + TX - 1) / TX, (n + TY - 1) / TY, (nz + TZ - 1) / TZ);
-  if (value) hipLaunchKernelGGL(k_qggmrf<true>, grid, dim3(NT), 0, st, f, grad, value, nz, n, pr, scale);
-  else hipLaunchKernelGGL(k_qggmrf<false>, grid, dim3(NT), 0, st, f, grad, value, nz, n, pr, scale);
+  QgConst k;
+  const double inv_sigma = 1.0 / double(pr.sigma);
+  k.e = 2.f - pr.p;
+  k.elog = float(double(k.e) * std::log2(inv_sigma));
+  k.c = pr.c;
+  const float w[3] = {pr.w_face, pr.w_edge, pr.w_corner};
+  for (int c = 0; c < 3; ++c) {
+    const double a = double(scale) * 2.0 * double(pr.lambda) * inv_sigma * inv_sigma * double(w[c]);
+    k.ap[c] = float(a * double(pr.p));
+    k.a2c[c] = float(a * 2.0 * double(pr.c));
+    k.w[c] = w[c];
+  }
+  // H = lambda sum over ordered pairs = 2 lambda sum over unordered pairs
+  const double value_scale = 2.0 * double(pr.lambda) * inv_sigma * inv_sigma;
+  const int xt = (n + OWN - 1) / OWN, yt = (n + TY - 1) / TY;
+  // enough z-chunks for about eight wavefronts per SIMD
+  const long strips = long(xt) * yt;
+  const int chunks = int(std::max<long>(1, std::min<long>(nz, (8192 + strips - 1) / strips)));
+  const int zchunk = (nz + chunks - 1) / chunks;
+  const int nzc = (nz + zchunk - 1) / zchunk;
+  const long nwaves = strips * nzc;
+  const dim3 grid(unsigned((nwaves + QG_WAVES - 1) / QG_WAVES));
+  const bool p2 = pr.p == 2.f;
+  const int nw = int(nwaves);
+  const dim3 block(64 * QG_WAVES);
+  if (value) {
+    if (p2) hipLaunchKernelGGL(k_qggmrf_value<true>, grid, block, 0, st, f, grad, value, nz, n, k, xt, yt, zchunk, nw, value_scale);
+    else hipLaunchKernelGGL(k_qggmrf_value<false>, grid, block, 0, st, f, grad, value, nz, n, k, xt, yt, zchunk, nw, value_scale);
+  } else {
+    if (accumulate) {
+      if (p2) hipLaunchKernelGGL((k_qggmrf<true, true>), grid, block, 0, st, f, grad, nz, n, k, xt, yt, zchunk, nw);
+      else hipLaunchKernelGGL((k_qggmrf<false, true>), grid, block, 0, st, f, grad, nz, n, k, xt, yt, zchunk, nw);
+    } else {
+      if (p2) hipLaunchKernelGGL((k_qggmrf<true, false>), grid, block, 0, st, f, grad, nz, n, k, xt, yt, zchunk, nw);
+      else hipLaunchKernelGGL((k_qggmrf<false, false>), grid, block, 0, st, f, grad, nz, n, k, xt, yt, zchunk, nw);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -386,11 +547,11 @@ hipError_t launch_residual_norm(float* s, const float* b, size_t count, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_mbir_update(float* x, float* x_prev, float* y, const float* g, size_t count, float inv_L,
-                              int nonneg, int restart, double* state, hipStream_t st) {
+hipError_t launch_mbir_update(float* x, float* x_prev, float* y, float* g, size_t count, float inv_L,
+                              int nonneg, int restart, double* state, hipStream_t st, bool add_x_prev) {
   hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, state + kStDot, 0.0);
   hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state,
-                     static_cast<float*>(nullptr));
+                     static_cast<float*>(nullptr), add_x_prev ? static_cast<const float*>(x_prev) : nullptr);
   hipLaunchKernelGGL(k_mbir_finalize, dim3(1), dim3(1), 0, st, state, restart, 0);
   hipLaunchKernelGGL(k_mbir_update, dim3(4096), dim3(256), 0, st, x, x_prev, y, g, count, inv_L, nonneg, state);
   return hipGetLastError();
@@ -399,7 +560,8 @@ hipError_t launch_mbir_update(float* x, float* x_prev, float* y, const float* g,
 hipError_t launch_mbir_candidate(const float* x, float* x_prev, const float* y, const float* g, size_t count,
                                  float inv_L, int nonneg, double* state, hipStream_t st) {
   hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, state + kStDot, 0.0);
-  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state, x_prev);
+  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, const_cast<float*>(g), count, inv_L, nonneg,
+                     state, x_prev, static_cast<const float*>(nullptr));
   return hipGetLastError();
 }
 

@@ -12,9 +12,10 @@ struct PriorArgs {
   float w_face, w_edge, w_corner;
 };
 
-// grad += scale * dH/df over a [nz][n][n] volume; value (if not null) = H(f)
+// grad += scale * dH/df over a [nz][n][n] volume (grad = scale * dH/df when
+// accumulate is false and value is null); value (if not null) = H(f)
 hipError_t launch_qggmrf(const float* f, float* grad, double* value, int nz, int n, const PriorArgs& pr,
-                         float scale, hipStream_t st);
+                         float scale, hipStream_t st, bool accumulate = true);
 // s -= b
 hipError_t launch_residual(float* s, const float* b, size_t count, hipStream_t st);
 // s -= b and value = 1/2 sum (s - b)^2
@@ -35,9 +36,11 @@ enum {
   kStCount = 16
 };
 
-// restart test (restart != 0), momentum and the x/y update
-hipError_t launch_mbir_update(float* x, float* x_prev, float* y, const float* g, size_t count, float inv_L,
-                              int nonneg, int restart, double* state, hipStream_t st);
+// restart test (restart != 0), momentum and the x/y update; with add_x_prev
+// the gradient is g + x_prev (a part computed into x_prev, whose contents the
+// update overwrites), stored back into g first
+hipError_t launch_mbir_update(float* x, float* x_prev, float* y, float* g, size_t count, float inv_L,
+                              int nonneg, int restart, double* state, hipStream_t st, bool add_x_prev = false);
 // monotone step, first half: the restart dot product and the candidate
 // x' = y - g/L (clamped when nonneg) into x_prev
 hipError_t launch_mbir_candidate(const float* x, float* x_prev, const float* y, const float* g, size_t count,
