@@ -106,6 +106,13 @@ def model_bytes_per_slice(n: int, nd: int, na: int) -> float:
     return fwd + adj
 
 
+def mbir_model_bytes(n: int, nd: int, na: int, nz: int) -> float:
+    """Algorithmic bytes of one MBIR iteration over nz slices: the forward +
+    adjoint model of every slice, the data b read once and five volumes
+    streamed by the prior and the update (4 B each)."""
+    return nz * (model_bytes_per_slice(n, nd, na) + 4 * na * nd + 20 * n * n)
+
+
 def cpu_model() -> str | None:
     """The host CPU's model name (first "model name" line of /proc/cpuinfo)."""
     try:
@@ -183,27 +190,97 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
     out = {"volume": f"{nz} x {n}^2 random ellipsoids (20)", "n_angles": na, "data": "Poisson, 1e4 photons/bin",
            "iterations": iters, "prior": "qGGMRF p=1.2 sigma=1/0.7 c=1e-4 lambda=1, 26 neighbours",
            "tuning": MBIR_TUNING}
-    for name, fn in (("plain", "step"), ("autograd", "step_autograd")):
+    gb = mbir_model_bytes(n, n, na, nz) / 1e9
+    out["model_GB_per_iter"] = round(gb, 3)
+    for name, fn in (("plain", "step"), ("autograd", "step_autograd"), ("graph", None)):
+        # same iterations from the same start on every path; the graph path
+        # replays a capture of `timed` plain steps
         m = MBIR(plan, b, prior, L_data=L_data)
-        step = getattr(m, fn)
-        for _ in range(2):                        # warm-up (iterates restart below)
+        if fn is None:
+            graph = m.capture(timed)
+            step, per = graph.launch, timed
+        else:
+            step, per = getattr(m, fn), 1
+        for _ in range(max(1, 2 // per)):         # warm-up (iterates restart below)
             step()
         m = MBIR(plan, b, prior, L_data=L_data)
-        step = getattr(m, fn)
+        if fn is None:
+            graph.close()
+            graph = m.capture(timed)
+            step = graph.launch
+        else:
+            step = getattr(m, fn)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(timed):
+        for _ in range(timed // per):
             step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        for _ in range(iters - timed):
+        for _ in range((iters - timed) // per):
             step()
         torch.cuda.synchronize()
-        out[f"iters_per_s_{name}"] = round(timed / dt, 2)
+        if fn is None:
+            graph.close()
+        ips = timed / dt
+        out[f"iters_per_s_{name}"] = round(ips, 2)
+        out[f"frac_of_hbm_peak_{name}"] = round(gb * ips / HBM_PEAK_GBS, 4)
         out[f"recon_rel_err_{name}"] = round(err(m.x), 5)
         out[f"restarts_{name}"] = m.restarts
     plan.close()
     torch.cuda.synchronize()
+    return out
+
+
+# Full sparse-view MBIR: 128 slices of 2560^2, 361 angles, 30 ellipsoids with
+# 12 blurred cracks, Gaussian noise of 1 % of the largest datum, 100
+# iterations over the resident stack (the prior couples adjacent slices).
+CONFIG5_LAMBDA = 1.0
+
+
+def config5_leg(dev, iters: int = 100) -> dict:
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import MBIR, Plan, Prior, power_lipschitz
+
+    n, nz, na = 2560, 128, 361
+    vol64 = synth.ellipsoid_volume(5, n, nz, 30, device=dev)
+    vol = synth.add_cracks(vol64, synth.rng_for(5, 1), 12).to(torch.float32).contiguous()
+    del vol64
+    torch.cuda.empty_cache()
+    plan = Plan.uniform_stack(n, n, synth.uniform_angles(na), nz, device=dev)
+    b = torch.as_tensor(synth.gaussian_noise(plan.fwd(vol), synth.rng_for(5, 2), 0.01), dtype=torch.float32,
+                        device=dev).contiguous()
+    prior = Prior(lam=CONFIG5_LAMBDA)
+    L_data = power_lipschitz(plan, 30)
+    x_ = torch.arange(n, device=dev, dtype=torch.float32) - n // 2
+    mask = ((x_[None, :] ** 2 + x_[:, None] ** 2) <= (n / 2) ** 2).to(torch.float32)
+
+    def err(x):
+        return float(torch.linalg.vector_norm((x - vol) * mask) / torch.linalg.vector_norm(vol * mask))
+
+    m = MBIR(plan, b, prior, L_data=L_data)
+    m.step()                                      # warm-up, then restart from zero
+    m = MBIR(plan, b, prior, L_data=L_data)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.run(10)
+    torch.cuda.synchronize()
+    e10 = err(m.x)
+    t1 = time.perf_counter()
+    m.run(iters - 10)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) + (t1 - t0)
+    gb = mbir_model_bytes(n, n, na, nz) / 1e9
+    ips = iters / dt
+    out = {"volume": f"{nz} x {n}^2, 30 ellipsoids + 12 cracks", "n_angles": na, "data": "Gaussian noise 1% of max",
+           "iterations": iters, "lambda": CONFIG5_LAMBDA, "iters_per_s": round(ips, 2),
+           "model_GB_per_iter": round(gb, 2), "frac_of_hbm_peak": round(gb * ips / HBM_PEAK_GBS, 4),
+           "recon_rel_err_10": round(e10, 4), "recon_rel_err_final": round(err(m.x), 4), "restarts": m.restarts}
+    plan.close()
+    del m, vol, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -294,15 +371,36 @@ def batched_leg(dev, count: int, reps: int) -> dict:
     t_per = t(lambda: (per.fwd(vol, sino), per.adj(sino, back)))
     info = plan.info()
     graph.close()
-    plan.close()
     per.close()
+    # the same pass with each batch as one persistent kernel over per-XCD work
+    # queues (built for the 64x32 spreading tile), with the tuned batches and
+    # with the whole stack as one batch (one launch)
+    persistent = {}
+    for label, extra in (("tuned_batches", {}), ("one_batch", {"batch_mb": 1 << 20, "streams": 1})):
+        with Plan(geoms, device=dev, tuning={**tuning, "tile_w": 64, "tile_h": 32, "persistent": 1, **extra}) as pp:
+            g2 = pp.capture("fwd+adj", vol, sino, back)
+            t_p = t(g2.launch)
+            pp.check()
+            g2.close()
+            persistent[label] = {"graph_slices_per_s": round(count / t_p, 1), "batches": pp.info()["batches"],
+                                 "launches_per_pass": pp.info()["launches"]}
+    plan.close()
     torch.cuda.synchronize()
     sizes = {n: sum(1 for g in geoms if g.n == n) for n in (512, 1024, 2048)}
+    gb = sum(model_bytes_per_slice(g.n, g.n_det, len(g.angles)) for g in geoms) / 1e9
+    def frac(seconds):   # model bytes of one pass over its time, against the HBM peak
+        return round(gb / seconds / HBM_PEAK_GBS, 4)
+
+    for v in persistent.values():
+        v["frac_of_hbm_peak"] = frac(count / v["graph_slices_per_s"])
     return {"slices": count, "sizes": sizes, "angles_total": int(sum(len(g.angles) for g in geoms)),
+            "model_GB_per_pass": round(gb, 3),
             "batched_graph_slices_per_s": round(count / t_graph, 1),
+            "batched_graph_frac_of_hbm_peak": frac(t_graph),
             "per_slice_slices_per_s": round(count / t_per, 1),
+            "per_slice_frac_of_hbm_peak": frac(t_per),
             "speedup": round(t_per / t_graph, 3), "tuning": tuning, "batches": info["batches"], "slots": info["slots"],
-            "launches_per_pass": info["launches"]}
+            "launches_per_pass": info["launches"], "persistent": persistent}
 
 
 def device_copy_gbs(dev, stream, mib: int = 2048, reps: int = 5) -> float:
@@ -349,6 +447,7 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true", help="time without per-stage events")
     ap.add_argument("--no-mbir", action="store_true", help="skip the MBIR iterations/s leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-stack leg")
+    ap.add_argument("--no-config5", action="store_true", help="skip the 128 x 2560^2 sparse-view MBIR leg")
     ap.add_argument("--no-paper-shapes", action="store_true",
                     help="skip the 100-iteration MBIR runs at the paper's dataset shapes")
     ap.add_argument("--no-extensions", action="store_true",
@@ -558,6 +657,13 @@ def main() -> int:
         mbir = mbir_leg(dev, args.mbir_n, args.mbir_slices, args.mbir_angles, args.mbir_iters, 10)
         print(f"[bench] MBIR {mbir}", file=sys.stderr, flush=True)
 
+    config5 = None
+    if not args.no_config5:
+        torch.cuda.empty_cache()
+        print("[bench] sparse-view MBIR leg (128 x 2560^2) ...", file=sys.stderr, flush=True)
+        config5 = config5_leg(dev)
+        print(f"[bench] sparse-view MBIR {config5}", file=sys.stderr, flush=True)
+
     paper = None
     if not args.no_paper_shapes:
         torch.cuda.empty_cache()
@@ -607,6 +713,7 @@ def main() -> int:
         "step_frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
         "stages": stage_report,
         "mbir": mbir,
+        "mbir_sparse_view_2560": config5,
         "uneven_stack": batched,
         "paper_shapes_mbir": paper,
         "extensions": extensions,

@@ -154,6 +154,16 @@ nr_status nr_plan_destroy(nr_plan* plan);
  *                       overlap on the device
  *   "spread_mode"       0 = LDS-tiled spreading (default), 1 = one thread per
  *                       point with global float atomics (a slow cross-check)
+ *   "persistent"        1 = a forward + adjoint pass (radon_normal, and the
+ *                       fwd-then-adj graph) runs each batch as ONE persistent
+ *                       kernel: resident workgroups take the batch's units
+ *                       from per-XCD work queues (each slice's units on one
+ *                       XCD, stage-major) and wait, bounded, on per-slice
+ *                       stage counters; needs kernel width 7, the 64x32 tile,
+ *                       interp_mode 0 and FFT lengths 128..4096 (powers of
+ *                       two), else the layout fails with UNSUPPORTED_SIZE;
+ *                       0 (default) = one launch per stage.  Other calls and
+ *                       profiled runs use the per-stage launches.
  * Changing any key but spread_mode unbinds the plan: query
  * nr_plan_workspace_bytes and call nr_plan_bind again. */
 nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value);
@@ -370,6 +380,11 @@ nr_status nr_plan_get_tune(const nr_plan* plan, const char* key, int64_t* value)
  * piecewise-polynomial device approximation of phi at u[i]. */
 nr_status nr_kb_eval(int32_t width, double beta, int32_t count, const double* u, const double* xi,
                      double* phi, double* phihat, double* phi_poly);
+
+/* Synchronises `stream` and reports NR_INTERNAL if a persistent launch of
+ * the plan gave up waiting for a stage (a bounded wait ran out; the pass's
+ * results are then invalid), resetting the flag; NR_OK otherwise. */
+nr_status nr_plan_check(nr_plan* plan, nr_stream stream);
 
 /* Describe how a plan splits work: fills up to 8 counts for slice `index`:
  * info[0] = oversampled grid G, info[1] = spreading tiles, info[2] = tile

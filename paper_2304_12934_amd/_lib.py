@@ -105,6 +105,7 @@ SIGNATURES = {
     "nr_kb_eval": (c_int32, [c_int32, c_double, c_int32, POINTER(c_double), POINTER(c_double),
                              POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
     "nr_plan_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), c_int32]),
+    "nr_plan_check": (c_int32, [c_void_p, c_void_p]),
 }
 
 _LIB = None

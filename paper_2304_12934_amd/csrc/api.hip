@@ -49,6 +49,7 @@ struct nr_plan {
   // concurrent lanes: streams (default priority, non-blocking) plus the
   // events that fork them from and join them back to the caller's stream
   int lane_device = -1;
+  int persist_blocks = 0;   // resident workgroups of the persistent kernel (0: not queried yet)
   std::vector<hipStream_t> lanes;
   std::vector<hipEvent_t> lane_done;
   std::vector<hipEvent_t> lane_skew;
@@ -256,7 +257,41 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
   a.fbp_filter = fbp ? fbp->filter : -1;
   a.fbp_order = fbp ? fbp->order : 0;
   a.fbp_inv_cutoff = fbp && fbp->filter == NR_FBP_BUTTERWORTH ? float(1.0 / fbp->cutoff) : 0.f;
-  for (size_t bi = 0; bi < p.batches.size(); ++bi) {
+  // a forward + adjoint pass of a plan tuned persistent: each batch is one
+  // persistent launch (after a clear of its counters) on its lane
+  const bool persist = p.tune.persistent && fwd && adj && !plan->profiling && p.tune.spread_mode == 0;
+  if (persist && plan->persist_blocks <= 0) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, where);
+    const int per_cu = nrk::persist_blocks_per_cu(p.kb.W);
+    // at least one workgroup per XCD queue; a multiple of the queue count
+    plan->persist_blocks = std::max(kPersistQueues, per_cu * cus / kPersistQueues * kPersistQueues);
+  }
+  for (size_t bi = 0; persist && bi < p.batches.size(); ++bi) {
+    const nr::Batch& bt = p.batches[bi];
+    char* wsb = static_cast<char*>(p.d_ws);
+    const int32_t* tab = reinterpret_cast<const int32_t*>(wsb + p.off_ptables) + bt.pt_off;
+    int32_t* sync = reinterpret_cast<int32_t*>(wsb + p.off_psync);
+    const int n = int(bt.slices.size());
+    nrk::PersistArgs pa{};
+    pa.entries = reinterpret_cast<const PersistEntry*>(wsb + p.off_pentries) + bt.pe_first;
+    pa.qoff = tab;
+    pa.need = tab + kPersistQueues + 1;
+    pa.dep = pa.need + size_t(n) * kPersistStages;
+    pa.tickets = sync + bt.ps_off;
+    pa.done = pa.tickets + kPersistQueues;
+    pa.error = sync;
+    pa.first_slice = bt.slices.front();
+    pa.spin_limit = 1 << 18;   // about a second of polling: far beyond any unit's duration
+    nrk::LaunchArgs la = a;
+    la.sino_sub = b;
+    const hipError_t e = nrk::launch_persistent(la, pa, kb, p.kb.W, plan->persist_blocks, pa.tickets,
+                                                kPersistQueues + n * kPersistStages, lane_stream(bt));
+    if (e != hipSuccess) return hip_fail(e, where);
+  }
+  for (size_t bi = 0; !persist && bi < p.batches.size(); ++bi) {
     const nr::Batch& bt = p.batches[bi];
     hipStream_t bs = lane_stream(bt);
     std::vector<const nr::StageLaunch*> seq;
@@ -429,6 +464,8 @@ hipError_t upload_tables(const nr::Plan& p, char* base, const std::vector<SliceD
     if ((e = up(g.off_iitems, g.iitems.data(), g.iitems.size() * sizeof(SpreadItem)))) return e;
   }
   if ((e = up(p.off_desc, descs.data(), descs.size() * sizeof(SliceDesc)))) return e;
+  if ((e = up(p.off_pentries, p.pentries.data(), p.pentries.size() * sizeof(PersistEntry)))) return e;
+  if ((e = up(p.off_ptables, p.ptables.data(), p.ptables.size() * sizeof(int32_t)))) return e;
   return up(p.off_work, p.work.data(), p.work.size() * sizeof(WorkItem));
 }
 
@@ -545,6 +582,7 @@ int64_t tune_value(const nr::Tuning& t, const std::string& k) {
   if (k == "batch") return t.batch;
   if (k == "interp_mode") return t.interp_mode;
   if (k == "spread_mode") return t.spread_mode;
+  if (k == "persistent") return t.persistent;
   return INT64_MIN;
 }
 
@@ -643,6 +681,7 @@ nr_status nr_plan_bind(nr_plan* plan, void* d_ws, size_t bytes, nr_stream stream
   hipStream_t st = static_cast<hipStream_t>(stream);
   plan->host_descs = nr::slice_descs(p, static_cast<char*>(d_ws));
   hipError_t e = upload_tables(p, static_cast<char*>(d_ws), plan->host_descs, st);
+  if (!e) e = nrk::launch_fill_int(reinterpret_cast<int*>(static_cast<char*>(d_ws) + p.off_psync), p.psync_ints, 0, st);
   // the host tables are read by the copies: wait here so the caller may reuse
   // or destroy the plan freely afterwards
   if (!e) e = hipStreamSynchronize(st);
@@ -680,6 +719,9 @@ nr_status nr_plan_tune(nr_plan* plan, const char* key, int64_t value) {
   } else if (std::strcmp(key, "batch") == 0) {
     if (value < 0) return fail(NR_INVALID_ARG, "batch must be >= 0");
     t.batch = int(value);
+  } else if (std::strcmp(key, "persistent") == 0) {
+    if (value != 0 && value != 1) return fail(NR_INVALID_ARG, "persistent must be 0 or 1");
+    t.persistent = int(value);
   } else if (std::strcmp(key, "batch_mb") == 0) {
     if (value < 0 || value > (1 << 20)) return fail(NR_INVALID_ARG, "batch_mb must be in [0, 2^20]");
     t.batch_mb = int(value);
@@ -1283,6 +1325,23 @@ nr_status nr_autotune(nr_plan* plan, void* d_scratch, size_t bytes, const char* 
   return NR_OK;
 }
 
+nr_status nr_plan_check(nr_plan* plan, nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t flag = 0;
+  int32_t* d_flag = reinterpret_cast<int32_t*>(static_cast<char*>(plan->p.d_ws) + plan->p.off_psync);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpy(&flag, d_flag, sizeof(flag), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "nr_plan_check");
+  if (flag != 0) {
+    e = nrk::launch_fill_int(d_flag, 1, 0, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "nr_plan_check reset");
+    return fail(NR_INTERNAL, "a persistent launch gave up waiting for a stage (its results are invalid)");
+  }
+  return NR_OK;
+}
+
 nr_status nr_plan_info(const nr_plan* plan, int32_t index, int64_t* info, int32_t count) {
   if (!plan || !info) return fail(NR_INVALID_ARG, "plan/info is NULL");
   if (nr_status st = ensure_layout(const_cast<nr_plan*>(plan))) return st;
@@ -1290,7 +1349,8 @@ nr_status nr_plan_info(const nr_plan* plan, int32_t index, int64_t* info, int32_
   if (index < 0 || index >= int(p.slices.size())) return fail(NR_INVALID_ARG, "slice index out of range");
   const nr::Geom& g = p.geoms[size_t(p.slice_geom[size_t(index)])];
   int64_t launches = 0;
-  for (const nr::Batch& bt : p.batches) launches += int64_t(bt.fwd.size() + bt.adj.size());
+  for (const nr::Batch& bt : p.batches)
+    launches += p.tune.persistent ? 2 : int64_t(bt.fwd.size() + bt.adj.size());   // clear + persistent kernel
   const int64_t v[8] = {g.G, int64_t(g.tiles_x) * g.tiles_y, int64_t(g.pts.size()), int64_t(g.items.size()),
                         p.kb.D, p.n_slots, int64_t(p.batches.size()), launches};
   for (int i = 0; i < count && i < 8; ++i) info[i] = v[i];

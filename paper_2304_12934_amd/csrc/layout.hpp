@@ -51,3 +51,15 @@ struct SliceDesc {
 struct WorkItem {
   int32_t slice, unit;
 };
+
+// Persistent launch: one kernel runs a batch's whole forward + adjoint chain.
+// An entry names one unit of one stage (nr::Stage numbering) of one slice;
+// the entries form one queue per XCD (each slice's units all in the queue of
+// the XCD it is assigned to), stage-major within a queue, so that every unit
+// depends only on units earlier in its own queue.
+struct PersistEntry {
+  int32_t slice, stage, unit, L;
+};
+constexpr int kPersistStages = 9;   // dependency counters per slice, indexed by stage
+constexpr int kPersistQueues = 8;   // one queue per XCD
+

@@ -619,6 +619,81 @@ nr_status layout_plan(Plan& plan, std::string& err) {
     plan.batches.push_back(std::move(bt));
   }
 
+  // persistent launches: per batch, each slice's units go to one of
+  // kPersistQueues queues (one per XCD; slices assigned largest first to the
+  // least loaded queue by their forward + adjoint model bytes), stage-major
+  // in chain order within a queue; each unit waits for the whole previous
+  // non-empty stage of its slice
+  plan.pentries.clear();
+  plan.ptables.clear();
+  plan.psync_ints = 1;   // the error flag
+  if (tu.persistent) {
+    if (plan.kb.W != 7 || tu.tile_w != 64 || tu.tile_h != 32 || tu.interp_mode != 0) {
+      err = "persistent launches need kernel width 7, the 64x32 spreading tile and interp_mode 0";
+      return NR_UNSUPPORTED_SIZE;
+    }
+    for (const Geom& g : plan.geoms)
+      if (!persist_length_supported(g.G) || !persist_length_supported(g.key.n_det)) {
+        err = "persistent launches are built for FFT lengths 128..4096 (powers of two); slice has G = " +
+              std::to_string(g.G) + ", N_t = " + std::to_string(g.key.n_det);
+        return NR_UNSUPPORTED_SIZE;
+      }
+    const Stage chain[] = {Stage::FwdRows, Stage::FwdCols, Stage::FwdInterp, Stage::FwdRadial, Stage::AdjRadial,
+                           Stage::SpreadZero, Stage::Spread, Stage::AdjCols, Stage::AdjRows};
+    for (Batch& bt : plan.batches) {
+      const int n = int(bt.slices.size());
+      const int first = bt.slices.front();
+      // queue of each slice
+      std::vector<int> order(size_t(n), 0), queue_of(size_t(n), 0);
+      std::vector<double> bytes(size_t(n), 0.0), load(kPersistQueues, 0.0);
+      for (int k = 0; k < n; ++k) {
+        const Geom& g = plan.geoms[size_t(plan.slice_geom[size_t(bt.slices[size_t(k)])])];
+        const double N = g.key.n, half = g.G / 2 + 1, na = g.key.n_angles, H = g.H, nt = g.key.n_det;
+        bytes[size_t(k)] = 8 * N * N + 32 * N * half + g.G * half * (24.0 + 2.0 * M_PI) + 32 * na * H + 8 * na * nt;
+        order[size_t(k)] = k;
+      }
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return bytes[size_t(x)] > bytes[size_t(y)]; });
+      for (int k : order) {
+        const size_t qi = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+        queue_of[size_t(k)] = int(qi);
+        load[qi] += bytes[size_t(k)];
+      }
+      std::vector<std::vector<PersistEntry>> queues(kPersistQueues);
+      std::vector<int32_t> need(size_t(n) * kPersistStages, 0), dep(size_t(n) * kPersistStages, -1);
+      for (int pass = 0; pass < 2; ++pass)
+        for (const StageLaunch& sl : pass == 0 ? bt.fwd : bt.adj) {
+          const WorkItem* w = plan.work.data() + sl.work_off / sizeof(WorkItem);
+          for (int i = 0; i < sl.n_work; ++i) {
+            if (w[i].slice < 0) continue;
+            const int k = w[i].slice - first;
+            queues[size_t(queue_of[size_t(k)])].push_back({w[i].slice, int(sl.stage), w[i].unit, sl.L});
+            need[size_t(k) * kPersistStages + size_t(sl.stage)] += 1;
+          }
+        }
+      for (int k = 0; k < n; ++k) {
+        int prev = -1;
+        for (Stage st : chain) {
+          const size_t c = size_t(k) * kPersistStages + size_t(st);
+          dep[c] = prev < 0 ? -1 : int32_t(size_t(k) * kPersistStages + size_t(prev));
+          if (need[c] > 0) prev = int(st);
+        }
+      }
+      bt.pe_first = plan.pentries.size();
+      bt.pt_off = plan.ptables.size();
+      int32_t q0 = 0;
+      for (int qi = 0; qi < kPersistQueues; ++qi) {
+        plan.ptables.push_back(q0);
+        q0 += int32_t(queues[size_t(qi)].size());
+        plan.pentries.insert(plan.pentries.end(), queues[size_t(qi)].begin(), queues[size_t(qi)].end());
+      }
+      plan.ptables.push_back(q0);
+      plan.ptables.insert(plan.ptables.end(), need.begin(), need.end());
+      plan.ptables.insert(plan.ptables.end(), dep.begin(), dep.end());
+      bt.ps_off = plan.psync_ints;
+      plan.psync_ints += kPersistQueues + size_t(n) * kPersistStages;
+    }
+  }
+
   // workspace layout
   size_t off = 0;
   for (auto& kv : plan.deapod) {
@@ -653,6 +728,12 @@ nr_status layout_plan(Plan& plan, std::string& err) {
   off = align_up(off + size_t(ns) * sizeof(SliceDesc), 256);
   plan.off_work = off;
   off = align_up(off + std::max<size_t>(1, plan.work.size()) * sizeof(WorkItem), 256);
+  plan.off_pentries = off;
+  off = align_up(off + std::max<size_t>(1, plan.pentries.size()) * sizeof(PersistEntry), 256);
+  plan.off_ptables = off;
+  off = align_up(off + std::max<size_t>(1, plan.ptables.size()) * sizeof(int32_t), 256);
+  plan.off_psync = off;
+  off = align_up(off + plan.psync_ints * sizeof(int32_t), 256);
   // batches round-robin over the lanes; each lane has its own scratch area
   plan.n_lanes = std::max(1, std::min(tu.streams, int(plan.batches.size())));
   for (size_t b = 0; b < plan.batches.size(); ++b) plan.batches[b].lane = int(b % size_t(plan.n_lanes));
@@ -661,6 +742,8 @@ nr_status layout_plan(Plan& plan, std::string& err) {
   plan.laid_out = true;
   return NR_OK;
 }
+
+bool persist_length_supported(int L) { return L >= 128 && L <= 4096 && (L & (L - 1)) == 0; }
 
 std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
   std::vector<SliceDesc> out(plan.slices.size());

@@ -92,6 +92,7 @@ struct Tuning {
   int spread_mode = 0;            // 0: LDS tiles, 1: global atomics (reference)
   int interp_mode = 0;            // 0: LDS tiles + radial pass, 1: direct gathers per angle pair
   int streams = 2;                // batches run round-robin on this many concurrent streams
+  int persistent = 0;             // 1: a forward + adjoint pass runs each batch as one persistent launch
 };
 
 // Stages of the forward chain (FwdRows, FwdCols, FwdInterp, FwdRadial) and of the
@@ -114,6 +115,11 @@ struct Batch {
   std::vector<int> slices;
   std::vector<size_t> slot_off;   // scratch offset of each slice inside its lane's slot area
   std::vector<StageLaunch> fwd, adj;
+  // persistent launch (Tuning::persistent): entries [pe_first, pe_first + n)
+  // in Plan::pentries; at pt_off in Plan::ptables the kPersistQueues + 1
+  // queue offsets, then need[] and dep[] (kPersistStages per slice); at
+  // ps_off in the sync area the tickets (kPersistQueues) and done counters
+  size_t pe_first = 0, pt_off = 0, ps_off = 0;
 };
 
 struct Plan {
@@ -142,6 +148,12 @@ struct Plan {
   int n_lanes = 1;                  // concurrent streams in use (at most the number of batches)
   int n_slots = 0;                  // most slices in one batch
   size_t ws_bytes = 0;
+  // persistent launches: every batch's entries, its tables, the sync area
+  // (int32: the error flag at 0, then each batch's tickets and counters)
+  std::vector<PersistEntry> pentries;
+  std::vector<int32_t> ptables;
+  size_t psync_ints = 0;
+  size_t off_pentries = 0, off_ptables = 0, off_psync = 0;
 
   void* d_ws = nullptr;
   size_t d_ws_bytes = 0;
@@ -154,6 +166,9 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
 // Spreading bins (for the current tuning), batches, work lists and the
 // workspace layout.  Idempotent until the tuning changes.
 nr_status layout_plan(Plan& plan, std::string& err);
+
+// FFT lengths the persistent kernel is built for (128..4096, powers of two).
+bool persist_length_supported(int L);
 
 // Per-slice descriptors with absolute pointers into the workspace at d_ws.
 std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws);

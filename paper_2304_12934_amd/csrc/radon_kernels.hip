@@ -38,6 +38,7 @@
 // SliceDesc.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fft.hpp"
@@ -54,8 +55,8 @@ namespace nrk {
 // phi(u - g0 - i) from the piecewise polynomial in z = u - g0 - (W-1)/2.
 // The multiply and subtract are rounded separately so the host's spreading
 // bins see the same g0.
-template <int W>
-__device__ __forceinline__ void point_taps(double gx, double gy, int j, const KBArgs& kb, int& g0x,
+template <int W, class KB>
+__device__ __forceinline__ void point_taps(double gx, double gy, int j, const KB& kb, int& g0x,
                                            int& g0y, float* wx, float* wy) {
   constexpr int D = W + 2;
   const double ux = __dmul_rn(double(j), gx);
@@ -175,10 +176,10 @@ __device__ __forceinline__ float wave_max(float x) {
   return x;
 }
 template <int T>
-__device__ __forceinline__ float block_sum(float x, float* red) {
+__device__ __forceinline__ float block_sum(float x, float* red, int tid) {
   x = wave_sum(x);
   __syncthreads();   // red may still be read from a previous reduction
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  if ((tid & 63) == 0) red[tid >> 6] = x;
   __syncthreads();
   float r = 0.f;
 #pragma unroll
@@ -186,10 +187,10 @@ __device__ __forceinline__ float block_sum(float x, float* red) {
   return r;
 }
 template <int T>
-__device__ __forceinline__ float block_max(float x, float* red) {
+__device__ __forceinline__ float block_max(float x, float* red, int tid) {
   x = wave_max(x);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  if ((tid & 63) == 0) red[tid >> 6] = x;
   __syncthreads();
   float r = 0.f;
 #pragma unroll
@@ -202,6 +203,19 @@ __device__ __forceinline__ float block_max(float x, float* red) {
 #define NR_STRIDED(n, COUNT, T)                                                                       \
   _Pragma("unroll") for (int n##_it = 0, n = tid; n##_it < ((COUNT) + (T)-1) / (T); ++n##_it, n += (T)) \
     if ((COUNT) % (T) == 0 || n < (COUNT))
+
+// LDS extents of the tiled interpolation and spreading (shared by their
+// kernels and the persistent kernel).
+template <int W>
+struct InterpLds {
+  static constexpr int RW = kInterpTileW + W + 1, RH = kInterpTileH + W + 1;
+  static constexpr int RS = RW | 1;   // odd row stride of the planes
+};
+template <int W, int TW, int TH>
+struct SpreadLds {
+  static constexpr int AH = TH + 2 * W, AW = TW + 2 * W;   // tile with its apron
+  static constexpr int TS = AW + 1;                         // odd row stride: columns of lanes spread over banks
+};
 
 // Every kernel runs one unit of its work list per workgroup (block b takes
 // entry b); padding entries (slice < 0) and blocks past the list do nothing.
@@ -223,38 +237,39 @@ __device__ __forceinline__ size_t t4(int q, int p, int N) {
 // F1: rows (along x), two at a time, transposed store into T
 // ---------------------------------------------------------------------------
 
+template <int L, int T, class LA>
+__device__ __forceinline__ void fwd_rows_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+  const DSlice d = load_desc(a.descs + wi.slice);
+  constexpr int N = L / 2;   // G = 2N
+  const int iy0 = 2 * wi.unit;
+  const float* __restrict__ f0 = a.vol_in + d.vol_off + size_t(iy0) * N;
+  const float d0 = d.deapod[iy0], d1 = d.deapod[iy0 + 1];
+  // x = ix - N/2 sits at index x mod L; indices N/2 .. L - N/2 - 1 are the zero padding
+  const NR_G float* __restrict__ dp = d.deapod;
+  fft_lds_halfzero<L, T, false>(s, d.tw_G, tid, [&](int n) {
+    const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+    const float dx = dp[ix];
+    return make_float2(dx * d0 * f0[ix], dx * d1 * f0[N + ix]);
+  });
+  // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
+  NR_G float4* __restrict__ out = (NR_G float4*)d.T;
+  NR_STRIDED(q, L / 2 + 1, T) {
+    const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
+    float4 o;
+    o.x = 0.5f * (z1.x + z2.x);
+    o.y = 0.5f * (z1.y - z2.y);
+    o.z = 0.5f * (z1.y + z2.y);
+    o.w = 0.5f * (z2.x - z1.x);
+    out[t4(q, iy0 >> 1, N)] = o;
+  }
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_rows(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    constexpr int N = L / 2;   // G = 2N
-    const int iy0 = 2 * wi.unit;
-    const float* __restrict__ f0 = a.vol_in + d.vol_off + size_t(iy0) * N;
-    const float d0 = d.deapod[iy0], d1 = d.deapod[iy0 + 1];
-    // x = ix - N/2 sits at index x mod L; indices N/2 .. L - N/2 - 1 are the zero padding
-    const NR_G float* __restrict__ dp = d.deapod;
-    fft_lds_halfzero<L, T, false>(s, d.tw_G, tid, [&](int n) {
-      const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
-      const float dx = dp[ix];
-      return make_float2(dx * d0 * f0[ix], dx * d1 * f0[N + ix]);
-    });
-    // split the two real transforms: A = (Z_q + conj Z_-q)/2, B = (Z_q - conj Z_-q)/(2i)
-    NR_G float4* __restrict__ out = (NR_G float4*)d.T;
-    NR_STRIDED(q, L / 2 + 1, T) {
-      const float2 z1 = s[q], z2 = s[q == 0 ? 0 : L - q];
-      float4 o;
-      o.x = 0.5f * (z1.x + z2.x);
-      o.y = 0.5f * (z1.y - z2.y);
-      o.z = 0.5f * (z1.y + z2.y);
-      o.w = 0.5f * (z2.x - z1.x);
-      out[t4(q, iy0 >> 1, N)] = o;
-    }
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) fwd_rows_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -270,58 +285,59 @@ __device__ __forceinline__ void store_row(NR_G float2* row, int colpad, int n, f
   if (p < 2 * colpad) row[p + L] = v;                    // right pad: qy >= L/2
 }
 
+template <int L, int T, class LA>
+__device__ __forceinline__ void fwd_cols_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+  const int halo = a.halo, colpad = a.colpad;
+  const DSlice d = load_desc(a.descs + wi.slice);
+  constexpr int N = L / 2;   // G = 2N
+  const int cols = d.cols;
+  const int qx = wi.unit;
+  // y = iy - N/2 sits at index y mod L; row iy of column qx is half iy & 1
+  // of the tile entry t4(qx, iy / 2)
+  const NR_G float2* __restrict__ T2 = (const NR_G float2*)d.T;
+  fft_first_pass_from<L, T, false, true>(s, tid, [&](int n) {
+    const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+    return T2[2 * t4(qx, iy >> 1, N) + (iy & 1)];
+  });
+  NR_G float2* ext = d.ext;
+  NR_G float2* row = ext + size_t(qx + halo) * cols;
+  // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
+  NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+  NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+  fft_passes<L, T, false, 1>(s, d.tw_G, tid);
+  // only |q| <= rdisc is ever read: the natural indices n in [0, lim] and
+  // [L - lim, L) of this row (a cell's periodic copies lie farther out than
+  // the cell itself, and mirror rows keep |q_y|).  Stored from LDS by every
+  // thread: measured faster than storing from the last pass's registers,
+  // which for L = 5120 leaves a fifth of the threads idle.
+  const int r2 = d.rdisc * d.rdisc - qx * qx;
+  const int lim = r2 <= 0 ? -1 : int(sqrtf(float(r2)));
+  const bool full = lim >= L / 2;   // the whole row, q_y = -L/2 included
+  const int cnt = full ? L : 2 * lim + 1;
+  for (int k = tid; k < cnt; k += T) {
+    const int n = (full || k <= lim) ? k : L - cnt + k;
+    const float2 v = s[n];
+    store_row<L>(row, colpad, n, v);
+    const int nm = n == 0 ? 0 : L - n;
+    if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
+    if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+  }
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  const int halo = a.halo, colpad = a.colpad;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    constexpr int N = L / 2;   // G = 2N
-    const int cols = d.cols;
-    const int qx = wi.unit;
-    // y = iy - N/2 sits at index y mod L; row iy of column qx is half iy & 1
-    // of the tile entry t4(qx, iy / 2)
-    const NR_G float2* __restrict__ T2 = (const NR_G float2*)d.T;
-    fft_first_pass_from<L, T, false, true>(s, tid, [&](int n) {
-      const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
-      return T2[2 * t4(qx, iy >> 1, N) + (iy & 1)];
-    });
-    NR_G float2* ext = d.ext;
-    NR_G float2* row = ext + size_t(qx + halo) * cols;
-    // rows qx = -s (s = 1..halo) hold conj(G[s][-qy]); rows qx = L/2 + s hold conj(G[L/2 - s][-qy])
-    NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
-    NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    fft_passes<L, T, false, 1>(s, d.tw_G, tid);
-    // only |q| <= rdisc is ever read: the natural indices n in [0, lim] and
-    // [L - lim, L) of this row (a cell's periodic copies lie farther out than
-    // the cell itself, and mirror rows keep |q_y|).  Stored from LDS by every
-    // thread: measured faster than storing from the last pass's registers,
-    // which for L = 5120 leaves a fifth of the threads idle.
-    const int r2 = d.rdisc * d.rdisc - qx * qx;
-    const int lim = r2 <= 0 ? -1 : int(sqrtf(float(r2)));
-    const bool full = lim >= L / 2;   // the whole row, q_y = -L/2 included
-    const int cnt = full ? L : 2 * lim + 1;
-    for (int k = tid; k < cnt; k += T) {
-      const int n = (full || k <= lim) ? k : L - cnt + k;
-      const float2 v = s[n];
-      store_row<L>(row, colpad, n, v);
-      const int nm = n == 0 ? 0 : L - n;
-      if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
-      if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
-    }
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) fwd_cols_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
 // F3 + F4: interpolation onto two half-lines and the radial inverse DFT
 // ---------------------------------------------------------------------------
 
-template <int W>
-__device__ __forceinline__ float2 interp_point(const DSlice& d, int halo, int colpad, const KBArgs& kb,
+template <int W, class KB>
+__device__ __forceinline__ float2 interp_point(const DSlice& d, int halo, int colpad, const KB& kb,
                                                int ang, int j) {
   int g0x, g0y;
   float wx[W], wy[W];
@@ -350,8 +366,8 @@ __device__ __forceinline__ float2 interp_point(const DSlice& d, int halo, int co
 // bin m (t = m - N_t/2) is output index t mod N_t.  With a.sino_sub the
 // data b are subtracted as the rows are stored (the residual R f - b of the
 // data term, Sec. 3 eq. "objfn"), so no separate pass re-reads them.
-template <int L, int T>
-__device__ __forceinline__ void store_sino_rows(const LaunchArgs& a, const DSlice& d, int a0, bool has1, Lds s,
+template <int L, int T, class LA>
+__device__ __forceinline__ void store_sino_rows(const LA& a, const DSlice& d, int a0, bool has1, Lds s,
                                                 int tid) {
   const size_t off = d.sino_off + size_t(a0) * L;
   float* __restrict__ o0 = a.sino_out + off;
@@ -373,35 +389,36 @@ __device__ __forceinline__ void store_sino_rows(const LaunchArgs& a, const DSlic
   }
 }
 
+template <int L, int W, int T, class LA, class KB>
+__device__ __forceinline__ void fwd_interp_unit(const LA& a, const KB& kb, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+  const float inv = 1.0f / float(L);
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const int a0 = 2 * wi.unit, a1 = a0 + 1;
+  const bool has1 = a1 < d.na;
+  // both half-lines per iteration (two independent gathers in flight), packed
+  // as the Hermitian completions Z = X + iY
+  for (int j = tid; j <= L / 2; j += T) {
+    float2 X = c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a0, j), inv);
+    float2 Y = has1 ? c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a1, j), inv) : make_float2(0.f, 0.f);
+    if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
+      X.y = 0.f;
+      Y.y = 0.f;
+    }
+    s[j] = make_float2(X.x - Y.y, X.y + Y.x);
+    if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
+  }
+  __syncthreads();
+  fft_lds<L, T, true>(s, d.tw_Nt, tid);
+  // bin m (t = m - N_t/2) is output index t mod N_t
+  store_sino_rows<L, T>(a, d, a0, has1, s, tid);
+  __syncthreads();
+}
+
 template <int L, int W>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBArgs kb) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  const float inv = 1.0f / float(L);
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const int a0 = 2 * wi.unit, a1 = a0 + 1;
-    const bool has1 = a1 < d.na;
-    // both half-lines per iteration (two independent gathers in flight), packed
-    // as the Hermitian completions Z = X + iY
-    for (int j = tid; j <= L / 2; j += T) {
-      float2 X = c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a0, j), inv);
-      float2 Y = has1 ? c_scale(interp_point<W>(d, a.halo, a.colpad, kb, a1, j), inv) : make_float2(0.f, 0.f);
-      if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
-        X.y = 0.f;
-        Y.y = 0.f;
-      }
-      s[j] = make_float2(X.x - Y.y, X.y + Y.x);
-      if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
-    }
-    __syncthreads();
-    fft_lds<L, T, true>(s, d.tw_Nt, tid);
-    // bin m (t = m - N_t/2) is output index t mod N_t
-    store_sino_rows<L, T>(a, d, a0, has1, s, tid);
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) fwd_interp_unit<L, W, fft_threads(L)>(a, kb, wi, sbuf, int(threadIdx.x));
 }
 
 // F3 from LDS tiles: one work item = one interpolation tile and a range of the
@@ -413,115 +430,117 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
 // row stride: neighbouring lanes take neighbouring points of one line, about
 // two cells apart, and an even stride (interleaved complex values) put them
 // on a few LDS banks.
+template <int W, class LA, class KB>
+__device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, float* reg_re, float* reg_im, const int tid) {
+  constexpr int TW = kInterpTileW, TH = kInterpTileH;
+  constexpr int RW = InterpLds<W>::RW, RH = InterpLds<W>::RH, RS = InterpLds<W>::RS;
+  constexpr int T = 256, PER = kMaxChunk / T;
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const SpreadItem it = d.iitems[wi.unit];
+  // the thread's points and their angle tables, loaded up front (slots past
+  // the item's end repeat its first point; items are never empty),
+  // overlapping the tile staging
+  int pids[PER], fl[PER];
+  double gx[PER], gy[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = tid + k * T;
+    pids[k] = d.ipts[it.begin + (e < it.end - it.begin ? e : 0)];
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int ang = pids[k] / d.H;
+    gx[k] = d.gxy[2 * ang];
+    gy[k] = d.gxy[2 * ang + 1];
+    fl[k] = d.flip[ang];
+  }
+  const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 1;
+  const NR_G float2* __restrict__ ext = d.ext;
+  // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
+  NR_STRIDED(c, RH * RW, T) {
+    const int rl = c / RW, cl = c % RW;
+    const int r = min(max(r0 + rl, 0), d.rows - 1);
+    const int cc = min(max(c0 + cl, 0), d.cols - 1);
+    const float2 v = ext[size_t(r) * d.cols + cc];
+    reg_re[rl * RS + cl] = v.x;
+    reg_im[rl * RS + cl] = v.y;
+  }
+  __syncthreads();
+  const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
+  const float inv = 1.0f / float(d.Nt);
+  const int count = it.end - it.begin;   // at most kMaxChunk
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (k * T >= count) break;          // uniform over the workgroup
+    if (tid + k * T >= count) continue;
+    const int pid = pids[k];
+    const int ang = pid / d.H, j = pid - ang * d.H;
+    int g0x, g0y;
+    float wx[W], wy[W];
+    point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
+    const int o = (g0x + rb) * RS + (g0y + cb);
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int l = 0; l < W; ++l) {
+        const float2 v = make_float2(reg_re[o + i * RS + l], reg_im[o + i * RS + l]);
+        r.x = fmaf(wy[l], v.x, r.x);
+        r.y = fmaf(wy[l], v.y, r.y);
+      }
+      acc.x = fmaf(wx[i], r.x, acc.x);
+      acc.y = fmaf(wx[i], r.y, acc.y);
+    }
+    if (fl[k]) acc.y = -acc.y;
+    d.yh[pid] = c_scale(acc, inv);
+  }
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
-  constexpr int TW = kInterpTileW, TH = kInterpTileH;
-  constexpr int RW = TW + W + 1, RH = TH + W + 1;
-  constexpr int RS = RW | 1;   // odd row stride of the planes
-  constexpr int T = 256, PER = kMaxChunk / T;
-  __shared__ float reg_re[RH * RS];
-  __shared__ float reg_im[RH * RS];
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const SpreadItem it = d.iitems[wi.unit];
-    // the thread's points and their angle tables, loaded up front (slots past
-    // the item's end repeat its first point; items are never empty),
-    // overlapping the tile staging
-    int pids[PER], fl[PER];
-    double gx[PER], gy[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * T;
-      pids[k] = d.ipts[it.begin + (e < it.end - it.begin ? e : 0)];
-    }
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int ang = pids[k] / d.H;
-      gx[k] = d.gxy[2 * ang];
-      gy[k] = d.gxy[2 * ang + 1];
-      fl[k] = d.flip[ang];
-    }
-    const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 1;
-    const NR_G float2* __restrict__ ext = d.ext;
-    // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
-    NR_STRIDED(c, RH * RW, T) {
-      const int rl = c / RW, cl = c % RW;
-      const int r = min(max(r0 + rl, 0), d.rows - 1);
-      const int cc = min(max(c0 + cl, 0), d.cols - 1);
-      const float2 v = ext[size_t(r) * d.cols + cc];
-      reg_re[rl * RS + cl] = v.x;
-      reg_im[rl * RS + cl] = v.y;
-    }
-    __syncthreads();
-    const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
-    const float inv = 1.0f / float(d.Nt);
-    const int count = it.end - it.begin;   // at most kMaxChunk
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if (k * T >= count) break;          // uniform over the workgroup
-      if (tid + k * T >= count) continue;
-      const int pid = pids[k];
-      const int ang = pid / d.H, j = pid - ang * d.H;
-      int g0x, g0y;
-      float wx[W], wy[W];
-      point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
-      const int o = (g0x + rb) * RS + (g0y + cb);
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        float2 r = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int l = 0; l < W; ++l) {
-          const float2 v = make_float2(reg_re[o + i * RS + l], reg_im[o + i * RS + l]);
-          r.x = fmaf(wy[l], v.x, r.x);
-          r.y = fmaf(wy[l], v.y, r.y);
-        }
-        acc.x = fmaf(wx[i], r.x, acc.x);
-        acc.y = fmaf(wx[i], r.y, acc.y);
-      }
-      if (fl[k]) acc.y = -acc.y;
-      d.yh[pid] = c_scale(acc, inv);
-    }
-  }
+  __shared__ float reg_re[InterpLds<W>::RH * InterpLds<W>::RS];
+  __shared__ float reg_im[InterpLds<W>::RH * InterpLds<W>::RS];
+  NR_FOR_EACH_UNIT(a, wi) interp_tiles_unit<W>(a, kb, wi, reg_re, reg_im, int(threadIdx.x));
 }
 
 // F4 after k_interp_tiles: per pair of angles, the Hermitian completions of
 // the two half-lines packed as Z = X + iY, the inverse DFT along the line and
 // the real sinogram rows.
+template <int L, int T, class LA>
+__device__ __forceinline__ void fwd_radial_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+  constexpr int H = L / 2 + 1;
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const int a0 = 2 * wi.unit, a1 = a0 + 1;
+  const bool has1 = a1 < d.na;
+  const NR_G float2* __restrict__ x0 = d.yh + size_t(a0) * H;
+  const NR_G float2* __restrict__ x1 = has1 ? x0 + H : x0;   // loads stay unconditional
+  NR_STRIDED(j, H, T) {
+    float2 X = x0[j], Y = x1[j];
+    if (!has1) Y = make_float2(0.f, 0.f);
+    if (d.shift) {   // rotation axis at bin L/2 + c: evaluate the line at t - c
+      const float2 p = d.shift[j];
+      X = c_mul(X, p);
+      Y = c_mul(Y, p);
+    }
+    if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
+      X.y = 0.f;
+      Y.y = 0.f;
+    }
+    s[j] = make_float2(X.x - Y.y, X.y + Y.x);
+    if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
+  }
+  __syncthreads();
+  fft_lds<L, T, true>(s, d.tw_Nt, tid);
+  store_sino_rows<L, T>(a, d, a0, has1, s, tid);
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
-  constexpr int H = L / 2 + 1;
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const int a0 = 2 * wi.unit, a1 = a0 + 1;
-    const bool has1 = a1 < d.na;
-    const NR_G float2* __restrict__ x0 = d.yh + size_t(a0) * H;
-    const NR_G float2* __restrict__ x1 = has1 ? x0 + H : x0;   // loads stay unconditional
-    NR_STRIDED(j, H, T) {
-      float2 X = x0[j], Y = x1[j];
-      if (!has1) Y = make_float2(0.f, 0.f);
-      if (d.shift) {   // rotation axis at bin L/2 + c: evaluate the line at t - c
-        const float2 p = d.shift[j];
-        X = c_mul(X, p);
-        Y = c_mul(Y, p);
-      }
-      if (j == 0 || j == L / 2) {   // the full line's sum is real: keep Re at k = 0 and k = -1/2
-        X.y = 0.f;
-        Y.y = 0.f;
-      }
-      s[j] = make_float2(X.x - Y.y, X.y + Y.x);
-      if (j > 0 && j < L / 2) s[L - j] = make_float2(X.x + Y.y, Y.x - X.y);
-    }
-    __syncthreads();
-    fft_lds<L, T, true>(s, d.tw_Nt, tid);
-    store_sino_rows<L, T>(a, d, a0, has1, s, tid);
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) fwd_radial_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -531,7 +550,8 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_radial(LaunchArgs a) {
 // Filtered back-projection weight of half-line index j of an L-point line:
 // (pi/n_angles) |k| B(k) with k = j/L cycles per pixel and B = 1 (ramp) or
 // 1/(1 + (k/cutoff)^(2 order)) (Butterworth).
-__device__ __forceinline__ float fbp_weight(const LaunchArgs& a, int j, int L, int n_angles) {
+template <class LA>
+__device__ __forceinline__ float fbp_weight(const LA& a, int j, int L, int n_angles) {
   const float k = float(j) / float(L);
   float w = k;
   if (a.fbp_filter == 1) {
@@ -543,43 +563,45 @@ __device__ __forceinline__ float fbp_weight(const LaunchArgs& a, int j, int L, i
   return w * (3.14159265358979f / float(n_angles));
 }
 
+template <int L, int T, class LA>
+__device__ __forceinline__ void adj_radial_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const int a0 = 2 * wi.unit, a1 = a0 + 1;
+  const bool has1 = a1 < d.na;
+  const float* __restrict__ y0 = a.sino_in + d.sino_off + size_t(a0) * L;
+  const float* __restrict__ y1 = has1 ? y0 + L : y0;   // loads stay unconditional
+  NR_STRIDED(m, L, T) {
+    const float b = y1[m];
+    s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? b : 0.f);
+  }
+  __syncthreads();
+  fft_lds<L, T, false>(s, d.tw_Nt, tid);
+  const int H = L / 2 + 1;
+  NR_G float2* __restrict__ o0 = d.yh + size_t(a0) * H;
+  const float inv = 1.0f / float(L);
+  NR_STRIDED(j, H, T) {
+    const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
+    float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
+    if (a.fbp_filter >= 0) w *= fbp_weight(a, j, L, d.na);
+    float2 A = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
+    float2 B = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
+    if (d.shift) {   // transpose of the forward's phase
+      const float2 q = c_conj(d.shift[j]);
+      A = c_mul(A, q);
+      B = c_mul(B, q);
+    }
+    o0[j] = A;
+    if (has1) o0[H + j] = B;
+  }
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_radial(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const int a0 = 2 * wi.unit, a1 = a0 + 1;
-    const bool has1 = a1 < d.na;
-    const float* __restrict__ y0 = a.sino_in + d.sino_off + size_t(a0) * L;
-    const float* __restrict__ y1 = has1 ? y0 + L : y0;   // loads stay unconditional
-    NR_STRIDED(m, L, T) {
-      const float b = y1[m];
-      s[wrap_index<L>(m + L / 2)] = make_float2(y0[m], has1 ? b : 0.f);
-    }
-    __syncthreads();
-    fft_lds<L, T, false>(s, d.tw_Nt, tid);
-    const int H = L / 2 + 1;
-    NR_G float2* __restrict__ o0 = d.yh + size_t(a0) * H;
-    const float inv = 1.0f / float(L);
-    NR_STRIDED(j, H, T) {
-      const float2 z1 = s[j], z2 = s[j == 0 ? 0 : L - j];
-      float w = (j == 0 || j == L / 2) ? inv : 2.0f * inv;
-      if (a.fbp_filter >= 0) w *= fbp_weight(a, j, L, d.na);
-      float2 A = make_float2(0.5f * w * (z1.x + z2.x), 0.5f * w * (z1.y - z2.y));
-      float2 B = make_float2(0.5f * w * (z1.y + z2.y), 0.5f * w * (z2.x - z1.x));
-      if (d.shift) {   // transpose of the forward's phase
-        const float2 q = c_conj(d.shift[j]);
-        A = c_mul(A, q);
-        B = c_mul(B, q);
-      }
-      o0[j] = A;
-      if (has1) o0[H + j] = B;
-    }
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) adj_radial_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -592,18 +614,22 @@ __global__ void k_fill_zero(float4* p, size_t n4) {
 }
 
 // clear the tiles that several work items accumulate into
+template <int TW, int TH, class LA>
+__device__ __forceinline__ void spread_zero_unit(const LA& a, const WorkItem wi, const int tid) {
+
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const int t = d.zero_tiles[wi.unit];
+  const int r0 = (t / d.tiles_x) * TH, c0 = (t % d.tiles_x) * TW;
+  NR_G float2* ext = d.ext;
+  for (int c = tid; c < TW * TH; c += 256) {
+    const int r = r0 + c / TW, cc = c0 + c % TW;
+    if (r < d.rows && cc < d.cols) ext[size_t(r) * d.cols + cc] = make_float2(0.f, 0.f);
+  }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_spread_zero(LaunchArgs a) {
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const int t = d.zero_tiles[wi.unit];
-    const int r0 = (t / d.tiles_x) * TH, c0 = (t % d.tiles_x) * TW;
-    NR_G float2* ext = d.ext;
-    for (int c = threadIdx.x; c < TW * TH; c += 256) {
-      const int r = r0 + c / TW, cc = c0 + c % TW;
-      if (r < d.rows && cc < d.cols) ext[size_t(r) * d.cols + cc] = make_float2(0.f, 0.f);
-    }
-  }
+  NR_FOR_EACH_UNIT(a, wi) spread_zero_unit<TW, TH>(a, wi, int(threadIdx.x));
 }
 
 // One work item = one grid tile (TH rows x TW columns) and a range of the
@@ -621,153 +647,154 @@ __global__ __launch_bounds__(256) void k_spread_zero(LaunchArgs a) {
 // bounds test (no divergence); the apron is dropped at the end.  Single-item
 // tiles are then stored plainly (every cell, zeros included); shared tiles
 // are added with global float atomics.
+template <int W, int TW, int TH, class LA, class KB>
+__device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, int* acc_re, int* acc_im, float* red, int& nonfinite, const int tid) {
+  constexpr int AH = SpreadLds<W, TW, TH>::AH, AW = SpreadLds<W, TW, TH>::AW, TS = SpreadLds<W, TW, TH>::TS;
+  constexpr int T = 256, PER = kMaxChunk / T;
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const SpreadItem it = d.items[wi.unit];
+  const int count = it.end - it.begin;   // at most kMaxChunk
+  const NR_G float2* __restrict__ yh = d.yh;
+  // the thread's points: ids, values and angle tables, every load issued up
+  // front and kept in registers.  Slots past the item's end repeat its first
+  // point; an empty item (a tile no point touches, which still writes its
+  // zeros) reads no point list at all and uses point 0.
+  int pid[PER];
+  float2 v[PER];
+  double gx[PER], gy[PER];
+  int fl[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = tid + k * T;
+    pid[k] = count > 0 ? d.pts[it.begin + (e < count ? e : 0)] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int ang = pid[k] / d.H;
+    v[k] = yh[pid[k]];
+    gx[k] = d.gxy[2 * ang];
+    gy[k] = d.gxy[2 * ang + 1];
+    fl[k] = d.flip[ang];
+  }
+  for (int c = tid; c < AH * TS; c += T) {
+    acc_re[c] = 0;
+    acc_im[c] = 0;
+  }
+  const int r0 = (it.tile / d.tiles_x) * TH, c0 = (it.tile % d.tiles_x) * TW;
+  // apron coordinates of grid cell (row g0x + halo, column g0y + G/2 + colpad)
+  const int rbase = a.halo - r0 + W, cbase = d.G / 2 + a.colpad - c0 + W;
+  // k = 0 of every angle sits at the origin: their sum is spread once, in
+  // float32 when the tile is written out, so that it does not enter the
+  // item's fixed-point scale (with many angles it is far larger than any
+  // single point value and would coarsen every other contribution)
+  float dc = 0.f;
+  if (it.flags & kItemDC) {
+    float sum = 0.f;
+    for (int ang = tid; ang < d.na; ang += T) sum += yh[size_t(ang) * d.H].x;
+    dc = block_sum<T>(sum, red, tid);
+  }
+  // fixed-point scale of this item; a non-finite value (which the integer
+  // conversion would turn into 0) poisons the whole tile with NaN instead
+  float m = 0.f;
+  bool bad = !isfinite(dc);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (tid + k * T < count) {
+      m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+      bad |= !isfinite(v[k].x) || !isfinite(v[k].y);
+    }
+  }
+  if (tid == 0) nonfinite = 0;
+  const float mmax = block_max<T>(m, red, tid);   // synchronises: the tile is cleared
+  if (bad) nonfinite = 1;
+  const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
+  // one point per round; the slot's registers are picked with compile-time
+  // indices (no dynamic register indexing) and the taps are unrolled once
+#pragma unroll 1
+  for (int k = 0; k < PER; ++k) {
+    if (k * T >= count) break;          // uniform over the workgroup
+    int p = pid[0], f = fl[0];
+    float2 u = v[0];
+    double px = gx[0], py = gy[0];
+#pragma unroll
+    for (int z = 1; z < PER; ++z)
+      if (k == z) {
+        p = pid[z];
+        f = fl[z];
+        u = v[z];
+        px = gx[z];
+        py = gy[z];
+      }
+    if (tid + k * T < count) {
+      const int ang = p / d.H, j = p - ang * d.H;
+      if (f) u.y = -u.y;
+      u.x *= q;
+      u.y *= q;
+      int g0x, g0y;
+      float wx[W], wy[W];
+      point_taps<W>(px, py, j, kb, g0x, g0y, wx, wy);
+      const int base = (g0x + rbase) * TS + (g0y + cbase);
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        const float vx = wx[i] * u.x, vy = wx[i] * u.y;
+#pragma unroll
+        for (int l = 0; l < W; ++l) {
+          atomicAdd(&acc_re[base + i * TS + l], round_half_up(vx * wy[l]));
+          atomicAdd(&acc_im[base + i * TS + l], round_half_up(vy * wy[l]));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const bool shared_tile = it.flags & kItemAtomic;
+  const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
+  // the origin's W x W footprint in apron coordinates (DC items only)
+  int dcx = 0, dcy = 0;
+  float dwx[W], dwy[W];
+  const bool has_dc = it.flags & kItemDC;
+  if (has_dc) {
+    point_taps<W>(0.0, 0.0, 0, kb, dcx, dcy, dwx, dwy);
+    dcx += rbase;
+    dcy += cbase;
+  }
+  NR_G float2* ext = d.ext;
+  for (int c = tid; c < TH * TW; c += T) {
+    const int rl = c / TW, cl = c % TW;
+    const int r = r0 + rl, cc = c0 + cl;
+    if (r >= d.rows || cc >= d.cols) continue;
+    NR_G float2* dst = ext + size_t(r) * d.cols + cc;
+    const int ai = (rl + W) * TS + cl + W;
+    float re = float(acc_re[ai]) * inv_q;
+    const float im = float(acc_im[ai]) * inv_q;
+    if (has_dc) {
+      const int i = rl + W - dcx, l = cl + W - dcy;
+      if (i >= 0 && i < W && l >= 0 && l < W) {
+        float wi = 0.f, wl = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {   // compile-time register indices
+          if (k == i) wi = dwx[k];
+          if (k == l) wl = dwy[k];
+        }
+        re += dc * wi * wl;
+      }
+    }
+    if (shared_tile) {
+      atomicAdd((float*)&dst->x, re);
+      atomicAdd((float*)&dst->y, im);
+    } else {
+      *dst = make_float2(re, im);
+    }
+  }
+  __syncthreads();
+}
+
 template <int W, int TW, int TH>
 __global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
-  constexpr int AH = TH + 2 * W, AW = TW + 2 * W;   // tile with its apron
-  constexpr int TS = AW + 1;                         // odd row stride: columns of lanes spread over banks
-  constexpr int T = 256, PER = kMaxChunk / T;
-  __shared__ int acc_re[AH * TS];
-  __shared__ int acc_im[AH * TS];
-  __shared__ float red[T / 64];
+  __shared__ int acc_re[SpreadLds<W, TW, TH>::AH * SpreadLds<W, TW, TH>::TS];
+  __shared__ int acc_im[SpreadLds<W, TW, TH>::AH * SpreadLds<W, TW, TH>::TS];
+  __shared__ float red[4];
   __shared__ int nonfinite;
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const SpreadItem it = d.items[wi.unit];
-    const int count = it.end - it.begin;   // at most kMaxChunk
-    const NR_G float2* __restrict__ yh = d.yh;
-    // the thread's points: ids, values and angle tables, every load issued up
-    // front and kept in registers.  Slots past the item's end repeat its first
-    // point; an empty item (a tile no point touches, which still writes its
-    // zeros) reads no point list at all and uses point 0.
-    int pid[PER];
-    float2 v[PER];
-    double gx[PER], gy[PER];
-    int fl[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * T;
-      pid[k] = count > 0 ? d.pts[it.begin + (e < count ? e : 0)] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int ang = pid[k] / d.H;
-      v[k] = yh[pid[k]];
-      gx[k] = d.gxy[2 * ang];
-      gy[k] = d.gxy[2 * ang + 1];
-      fl[k] = d.flip[ang];
-    }
-    for (int c = tid; c < AH * TS; c += T) {
-      acc_re[c] = 0;
-      acc_im[c] = 0;
-    }
-    const int r0 = (it.tile / d.tiles_x) * TH, c0 = (it.tile % d.tiles_x) * TW;
-    // apron coordinates of grid cell (row g0x + halo, column g0y + G/2 + colpad)
-    const int rbase = a.halo - r0 + W, cbase = d.G / 2 + a.colpad - c0 + W;
-    // k = 0 of every angle sits at the origin: their sum is spread once, in
-    // float32 when the tile is written out, so that it does not enter the
-    // item's fixed-point scale (with many angles it is far larger than any
-    // single point value and would coarsen every other contribution)
-    float dc = 0.f;
-    if (it.flags & kItemDC) {
-      float sum = 0.f;
-      for (int ang = tid; ang < d.na; ang += T) sum += yh[size_t(ang) * d.H].x;
-      dc = block_sum<T>(sum, red);
-    }
-    // fixed-point scale of this item; a non-finite value (which the integer
-    // conversion would turn into 0) poisons the whole tile with NaN instead
-    float m = 0.f;
-    bool bad = !isfinite(dc);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if (tid + k * T < count) {
-        m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
-        bad |= !isfinite(v[k].x) || !isfinite(v[k].y);
-      }
-    }
-    if (tid == 0) nonfinite = 0;
-    const float mmax = block_max<T>(m, red);   // synchronises: the tile is cleared
-    if (bad) nonfinite = 1;
-    const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
-    // one point per round; the slot's registers are picked with compile-time
-    // indices (no dynamic register indexing) and the taps are unrolled once
-#pragma unroll 1
-    for (int k = 0; k < PER; ++k) {
-      if (k * T >= count) break;          // uniform over the workgroup
-      int p = pid[0], f = fl[0];
-      float2 u = v[0];
-      double px = gx[0], py = gy[0];
-#pragma unroll
-      for (int z = 1; z < PER; ++z)
-        if (k == z) {
-          p = pid[z];
-          f = fl[z];
-          u = v[z];
-          px = gx[z];
-          py = gy[z];
-        }
-      if (tid + k * T < count) {
-        const int ang = p / d.H, j = p - ang * d.H;
-        if (f) u.y = -u.y;
-        u.x *= q;
-        u.y *= q;
-        int g0x, g0y;
-        float wx[W], wy[W];
-        point_taps<W>(px, py, j, kb, g0x, g0y, wx, wy);
-        const int base = (g0x + rbase) * TS + (g0y + cbase);
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-          const float vx = wx[i] * u.x, vy = wx[i] * u.y;
-#pragma unroll
-          for (int l = 0; l < W; ++l) {
-            atomicAdd(&acc_re[base + i * TS + l], round_half_up(vx * wy[l]));
-            atomicAdd(&acc_im[base + i * TS + l], round_half_up(vy * wy[l]));
-          }
-        }
-      }
-    }
-    __syncthreads();
-    const bool shared_tile = it.flags & kItemAtomic;
-    const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
-    // the origin's W x W footprint in apron coordinates (DC items only)
-    int dcx = 0, dcy = 0;
-    float dwx[W], dwy[W];
-    const bool has_dc = it.flags & kItemDC;
-    if (has_dc) {
-      point_taps<W>(0.0, 0.0, 0, kb, dcx, dcy, dwx, dwy);
-      dcx += rbase;
-      dcy += cbase;
-    }
-    NR_G float2* ext = d.ext;
-    for (int c = tid; c < TH * TW; c += T) {
-      const int rl = c / TW, cl = c % TW;
-      const int r = r0 + rl, cc = c0 + cl;
-      if (r >= d.rows || cc >= d.cols) continue;
-      NR_G float2* dst = ext + size_t(r) * d.cols + cc;
-      const int ai = (rl + W) * TS + cl + W;
-      float re = float(acc_re[ai]) * inv_q;
-      const float im = float(acc_im[ai]) * inv_q;
-      if (has_dc) {
-        const int i = rl + W - dcx, l = cl + W - dcy;
-        if (i >= 0 && i < W && l >= 0 && l < W) {
-          float wi = 0.f, wl = 0.f;
-#pragma unroll
-          for (int k = 0; k < W; ++k) {   // compile-time register indices
-            if (k == i) wi = dwx[k];
-            if (k == l) wl = dwy[k];
-          }
-          re += dc * wi * wl;
-        }
-      }
-      if (shared_tile) {
-        atomicAdd((float*)&dst->x, re);
-        atomicAdd((float*)&dst->y, im);
-      } else {
-        *dst = make_float2(re, im);
-      }
-    }
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) spread_tiles_unit<W, TW, TH>(a, kb, wi, acc_re, acc_im, red, nonfinite, int(threadIdx.x));
 }
 
 // Reference spreading: one thread per polar point of one slice, global float
@@ -806,88 +833,279 @@ __device__ __forceinline__ float2 load_folded(const NR_G float2* row, int colpad
   return v;
 }
 
+template <int L, int T, class LA>
+__device__ __forceinline__ void adj_cols_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+  const int halo = a.halo, colpad = a.colpad;
+  const DSlice d = load_desc(a.descs + wi.slice);
+  const int qx = wi.unit;
+  const int cols = d.cols;
+  constexpr int N = L / 2;   // G = 2N
+  const NR_G float2* ext = d.ext;
+  const NR_G float2* row = ext + size_t(qx + halo) * cols;
+  const NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
+  const NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
+  // natural index n (q_y = n, or n - L from L/2 on) gathers the cell, its
+  // periodic copies (n within colpad of L/2) and, for the columns next to
+  // qx = 0 and G/2, the conjugate mirror rows.  Nothing is spread farther
+  // than rdisc from the origin (nor onto any copy of such a cell), so those
+  // cells are zero and not read.
+  const int r2 = d.rdisc * d.rdisc - qx * qx;
+  fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+    const int qy = n < L / 2 ? n : n - L;
+    if (qy * qy > r2) return make_float2(0.f, 0.f);
+    float2 v = load_folded<L>(row, colpad, n);
+    const int nm = n == 0 ? 0 : L - n;
+    if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+    if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+    return v;
+  });
+  // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
+  // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
+  NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
+  fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 v) {
+    const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+    T2[2 * t4(qx, iy >> 1, N) + (iy & 1)] = v;
+  });
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_cols(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  const int halo = a.halo, colpad = a.colpad;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    const int qx = wi.unit;
-    const int cols = d.cols;
-    constexpr int N = L / 2;   // G = 2N
-    const NR_G float2* ext = d.ext;
-    const NR_G float2* row = ext + size_t(qx + halo) * cols;
-    const NR_G float2* m1 = (qx >= 1 && qx <= halo) ? ext + size_t(halo - qx) * cols : nullptr;
-    const NR_G float2* m2 = (qx >= L / 2 - halo && qx <= L / 2 - 1) ? ext + size_t(L - qx + halo) * cols : nullptr;
-    // natural index n (q_y = n, or n - L from L/2 on) gathers the cell, its
-    // periodic copies (n within colpad of L/2) and, for the columns next to
-    // qx = 0 and G/2, the conjugate mirror rows.  Nothing is spread farther
-    // than rdisc from the origin (nor onto any copy of such a cell), so those
-    // cells are zero and not read.
-    const int r2 = d.rdisc * d.rdisc - qx * qx;
-    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
-      const int qy = n < L / 2 ? n : n - L;
-      if (qy * qy > r2) return make_float2(0.f, 0.f);
-      float2 v = load_folded<L>(row, colpad, n);
-      const int nm = n == 0 ? 0 : L - n;
-      if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
-      if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
-      return v;
-    });
-    // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
-    // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
-    NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
-    fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 v) {
-      const int iy = n < N / 2 ? n + N / 2 : n - (L - N / 2);
-      T2[2 * t4(qx, iy >> 1, N) + (iy & 1)] = v;
-    });
-    __syncthreads();
-  }
+  NR_FOR_EACH_UNIT(a, wi) adj_cols_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
 // A4: transpose of the row R2C: a'(x) = Re sum_{q=0}^{G/2} T'[q] e^{2 pi i q x/G}
 // ---------------------------------------------------------------------------
 
+template <int L, int T, class LA>
+__device__ __forceinline__ void adj_rows_unit(const LA& a, const WorkItem wi, float2* sbuf, const int tid) {
+  const Lds s{sbuf};
+
+  const DSlice d = load_desc(a.descs + wi.slice);
+  constexpr int N = L / 2;   // G = 2N
+  const int iy0 = 2 * wi.unit;
+  const NR_G float4* __restrict__ in = (const NR_G float4*)d.T;
+  // Hermitian completion with doubled real parts at q = 0 and G/2, two rows
+  // packed: index n <= L/2 takes entry q = n as X + iY, index L - q the
+  // conjugate-symmetric combination of the same entry
+  fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+    const int q = n <= L / 2 ? n : L - n;
+    const float4 t = in[t4(q, iy0 >> 1, N)];
+    float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
+    if (q == 0 || q == L / 2) {
+      X = make_float2(2.f * X.x, 0.f);
+      Y = make_float2(2.f * Y.x, 0.f);
+    }
+    return n <= L / 2 ? make_float2(X.x - Y.y, X.y + Y.x) : make_float2(X.x + Y.y, Y.x - X.y);
+  });
+  const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
+  float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
+  const NR_G float* __restrict__ dp = d.deapod;
+  // x = ix - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and [L - N/2, L)
+  fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 z) {
+    const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
+    const float dx = dp[ix];
+    g0[ix] = dx * d0 * z.x;
+    g0[N + ix] = dx * d1 * z.y;
+  });
+  __syncthreads();
+}
+
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_adj_rows(LaunchArgs a) {
-  constexpr int T = fft_threads(L);
   __shared__ float2 sbuf[lds_elems<L>()];
-  const Lds s{sbuf};
-  const int tid = threadIdx.x;
-  NR_FOR_EACH_UNIT(a, wi) {
-    const DSlice d = load_desc(a.descs + wi.slice);
-    constexpr int N = L / 2;   // G = 2N
-    const int iy0 = 2 * wi.unit;
-    const NR_G float4* __restrict__ in = (const NR_G float4*)d.T;
-    // Hermitian completion with doubled real parts at q = 0 and G/2, two rows
-    // packed: index n <= L/2 takes entry q = n as X + iY, index L - q the
-    // conjugate-symmetric combination of the same entry
-    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
-      const int q = n <= L / 2 ? n : L - n;
-      const float4 t = in[t4(q, iy0 >> 1, N)];
-      float2 X = make_float2(t.x, t.y), Y = make_float2(t.z, t.w);
-      if (q == 0 || q == L / 2) {
-        X = make_float2(2.f * X.x, 0.f);
-        Y = make_float2(2.f * Y.x, 0.f);
+  NR_FOR_EACH_UNIT(a, wi) adj_rows_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
+}
+
+// ---------------------------------------------------------------------------
+// M4: a batch's whole forward + adjoint chain in one persistent launch
+// ---------------------------------------------------------------------------
+//
+// A resident grid of 256-thread workgroups; each workgroup reads the id of the
+// XCD it runs on and takes tickets from that XCD's queue (an atomic counter).
+// A unit waits (one thread, bounded) until every unit of the stage before it
+// in its slice's chain has finished: units are counted per (slice, stage)
+// after their stores have completed.  A slice's units all run on one XCD, so
+// producer and consumer share that XCD's L2 (vector L1 is write-through): the
+// producer waits for its stores before counting, the consumer invalidates its
+// L1 after the wait, and no L2 writeback or invalidate is needed.  A wait
+// that exceeds the spin limit (or sees another's) sets the error flag and the
+// workgroup stops taking tickets, so every workgroup exits.
+
+constexpr int kPersistThreads = 256;
+
+// kernel-argument (constant) address space: loads through it are scalar
+#ifdef __HIP_DEVICE_COMPILE__
+#define NR_C __attribute__((address_space(4)))
+#else
+#define NR_C
+#endif
+
+template <int W>
+struct PersistLds {
+  static constexpr int FFT = 4096 * int(sizeof(float2));
+  static constexpr int SPREAD = 2 * SpreadLds<W, 64, 32>::AH * SpreadLds<W, 64, 32>::TS * int(sizeof(int));
+  static constexpr int INTERP = 2 * InterpLds<W>::RH * InterpLds<W>::RS * int(sizeof(float));
+  static constexpr int BYTES = FFT > SPREAD ? (FFT > INTERP ? FFT : INTERP) : (SPREAD > INTERP ? SPREAD : INTERP);
+};
+
+__device__ __forceinline__ int xcc_id() {
+  int x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & (kPersistQueues - 1);
+}
+
+#define NR_PERSIST_LENGTHS(X) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+template <int W, class LA, class KB>
+__device__ __forceinline__ void persist_unit(const LA& a, const KB& kb, int stage, int L, WorkItem wi,
+                                             char* lds, float* red, int& nonfinite, const int tid) {
+  float2* f2 = reinterpret_cast<float2*>(lds);
+  constexpr int T = kPersistThreads;
+  switch (StageKind(stage)) {
+    case StageKind::FwdRows:
+      switch (L) {
+#define NR_CASE(l) case l: fwd_rows_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
       }
-      return n <= L / 2 ? make_float2(X.x - Y.y, X.y + Y.x) : make_float2(X.x + Y.y, Y.x - X.y);
-    });
-    const float d0 = 0.5f * d.deapod[iy0], d1 = 0.5f * d.deapod[iy0 + 1];
-    float* __restrict__ g0 = a.vol_out + d.vol_off + size_t(iy0) * N;
-    const NR_G float* __restrict__ dp = d.deapod;
-    // x = ix - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and [L - N/2, L)
-    fft_lds_store_out<L, T, true, 1>(s, d.tw_G, tid, [&](int n, float2 z) {
-      const int ix = n < N / 2 ? n + N / 2 : n - (L - N / 2);
-      const float dx = dp[ix];
-      g0[ix] = dx * d0 * z.x;
-      g0[N + ix] = dx * d1 * z.y;
-    });
-    __syncthreads();
+      return;
+    case StageKind::FwdCols:
+      switch (L) {
+#define NR_CASE(l) case l: fwd_cols_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      return;
+    case StageKind::FwdInterp: {
+      float* re = reinterpret_cast<float*>(lds);
+      interp_tiles_unit<W>(a, kb, wi, re, re + InterpLds<W>::RH * InterpLds<W>::RS, tid);
+      return;
+    }
+    case StageKind::FwdRadial:
+      switch (L) {
+#define NR_CASE(l) case l: fwd_radial_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      return;
+    case StageKind::AdjRadial:
+      switch (L) {
+#define NR_CASE(l) case l: adj_radial_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      return;
+    case StageKind::SpreadZero:
+      spread_zero_unit<64, 32>(a, wi, tid);
+      return;
+    case StageKind::Spread: {
+      int* re = reinterpret_cast<int*>(lds);
+      spread_tiles_unit<W, 64, 32>(a, kb, wi, re, re + SpreadLds<W, 64, 32>::AH * SpreadLds<W, 64, 32>::TS, red,
+                                   nonfinite, tid);
+      return;
+    }
+    case StageKind::AdjCols:
+      switch (L) {
+#define NR_CASE(l) case l: adj_cols_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      return;
+    case StageKind::AdjRows:
+      switch (L) {
+#define NR_CASE(l) case l: adj_rows_unit<l, T>(a, wi, f2, tid); return;
+        NR_PERSIST_LENGTHS(NR_CASE)
+#undef NR_CASE
+      }
+      return;
+    default:
+      return;
   }
+}
+
+template <int W>
+__global__ __launch_bounds__(kPersistThreads) void k_persistent(PersistLaunch args) {
+  __shared__ __attribute__((aligned(16))) char lds[PersistLds<W>::BYTES];
+  __shared__ float red[kPersistThreads / 64];
+  __shared__ int nonfinite;
+  __shared__ int s_ticket, s_verdict;
+  // the arguments are read through the kernel-argument segment itself (the
+  // kernel's only parameter starts it), so no copy of them is made
+  const NR_C PersistLaunch* P = (const NR_C PersistLaunch*)__builtin_amdgcn_kernarg_segment_ptr();
+  const PersistArgs p = P->p;
+  const int q = xcc_id();
+  const int q0 = p.qoff[q], qn = p.qoff[q + 1] - q0;
+  const bool lead = threadIdx.x == 0;
+  // Every loop and every barrier below runs in workgroup-uniform control flow
+  // (loop exits come through readfirstlane of a value one thread published
+  // in LDS); the only divergent code is single stores and loads of thread 0,
+  // each fenced off by barriers.  A loop whose body mixes a divergent region
+  // and barriers can otherwise be restructured so that lanes of one
+  // wavefront loop back to a barrier without the lane that owns the ticket.
+  for (;;) {
+    __syncthreads();   // the previous unit's reads of LDS and of s_ticket are done
+    // one ticket per workgroup: thread 0 adds 1, the others 0 (no branch)
+    const int mine = atomicAdd(&p.tickets[q], lead ? 1 : 0);
+    if (lead) s_ticket = mine;
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (t >= qn) break;
+    const PersistEntry e = p.entries[q0 + t];
+    const int c = p.dep[(e.slice - p.first_slice) * kPersistStages + e.stage];
+    if (c >= 0) {
+      // wait, bounded, until the previous stage of this slice has finished:
+      // verdict 1 = go, 2 = give up (spin limit, or another gave up)
+      const int need = p.need[c];
+      int verdict = 0;
+      for (int spin = 0; verdict == 0; ++spin) {
+        if (lead) {
+          int v = 0;
+          if (__hip_atomic_load(&p.done[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) v = 1;
+          else if (spin >= p.spin_limit || __hip_atomic_load(p.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            v = 2;
+          s_verdict = v;
+        }
+        __syncthreads();
+        verdict = __builtin_amdgcn_readfirstlane(s_verdict);
+        __syncthreads();
+        if (verdict == 0) __builtin_amdgcn_s_sleep(2);
+      }
+      if (verdict == 2) {
+        if (lead) __hip_atomic_store(p.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    // the producers' stores are in this XCD's L2; drop stale lines from L1
+    asm volatile("buffer_inv sc0" ::: "memory");
+    // the launch and kernel arguments are read where each unit uses them
+    // (scalar loads from the argument segment), not held in registers across
+    // the loop: the laundered pointer is not loop-invariant to the compiler
+    const NR_C PersistLaunch* ap = P;
+    asm volatile("" : "+s"(ap));
+    // the thread index is laundered too: index arithmetic derived from it is
+    // recomputed per unit instead of being hoisted (and held) across the loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    persist_unit<W>(ap->a, ap->kb, e.stage, e.L, WorkItem{e.slice, e.unit}, lds, red, nonfinite, tid);
+    // every wave's stores have reached L2 before the unit is counted
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    atomicAdd(&p.done[(e.slice - p.first_slice) * kPersistStages + e.stage], lead ? 1 : 0);
+  }
+}
+
+// clears a batch's tickets and counters (before every persistent launch; a
+// kernel, so that graph capture records no memset)
+__global__ void k_persist_clear(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_fill_int(int* p, size_t n, int v) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -997,6 +1215,28 @@ hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArg
       break;
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(unsigned(std::min<size_t>(1024, (n + 255) / 256))), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+int persist_blocks_per_cu(int W) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (W == 7) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<7>, kPersistThreads, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_persistent(const LaunchArgs& a, const PersistArgs& p, const KBArgs& kb, int W, int blocks,
+                             int* clear, int clear_count, hipStream_t st) {
+  if (W != 7 || blocks < kPersistQueues) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_persist_clear, dim3(std::max(1, std::min(64, (clear_count + 255) / 256))), dim3(256), 0, st,
+                     clear, clear_count);
+  hipLaunchKernelGGL(k_persistent<7>, dim3(blocks), dim3(kPersistThreads), 0, st, PersistLaunch{a, p, kb});
+  return hipGetLastError();
 }
 
 hipError_t launch_spread_reference(const SliceDesc* d_descs, int slice, const SliceDesc& host_desc, int halo,

@@ -23,6 +23,21 @@ struct LaunchArgs {
   float fbp_inv_cutoff;
 };
 
+// Arguments of a persistent launch (one batch): the per-XCD queues of
+// entries, their offsets, the dependency tables of the batch's slices
+// (first_slice .. first_slice + n - 1) and the cleared counters.
+struct PersistArgs {
+  const PersistEntry* entries;
+  const int32_t* qoff;       // kPersistQueues + 1 offsets into entries
+  const int32_t* need;       // [slice][stage]: units of that stage
+  const int32_t* dep;        // [slice][stage]: counter to wait for (-1: none)
+  int32_t* tickets;          // kPersistQueues, cleared before the launch
+  int32_t* done;             // [slice][stage], cleared before the launch
+  int32_t* error;            // set when a wait gives up (not cleared by the launch)
+  int first_slice;
+  int spin_limit;
+};
+
 // Kaiser-Bessel tap polynomials: c[i*(W+3) + k] is the z^k coefficient of tap i.
 struct KBArgs {
   float c[8 * 11];
@@ -35,6 +50,23 @@ enum class StageKind : int { FwdRows = 0, FwdCols, FwdInterp, AdjRadial, Spread,
 // slices in the list (unused by the spreading stages).
 hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArgs& kb, int W, int tile_w,
                         int tile_h, hipStream_t st);
+
+// Everything a persistent launch reads, as the kernel's single argument.
+struct PersistLaunch {
+  LaunchArgs a;
+  PersistArgs p;
+  KBArgs kb;
+};
+
+// Persistent launch of a batch's forward + adjoint chain (W = 7, spreading
+// tile 64x32, FFT lengths 128..4096): clears `clear_count` ints at `clear`
+// (the tickets and counters), then runs `blocks` resident workgroups.
+hipError_t launch_persistent(const LaunchArgs& a, const PersistArgs& p, const KBArgs& kb, int W, int blocks,
+                             int* clear, int clear_count, hipStream_t st);
+// resident workgroups of the persistent kernel per CU (0 if W is not built)
+int persist_blocks_per_cu(int W);
+// p[0 .. n) = v
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t st);
 
 // Reference spreading of one slice (clear + one thread per point with
 // global float atomics); host_desc is the host copy of that slice's descriptor.

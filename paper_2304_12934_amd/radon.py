@@ -333,6 +333,12 @@ class Plan:
     def tune(self, key: str, value: int) -> None:
         check(lib().nr_plan_tune(self._h, key.encode(), int(value)), "nr_plan_tune")
 
+    def check(self) -> None:
+        """Synchronise the current stream and raise if a persistent launch of
+        this plan gave up waiting for a stage (``nr_plan_check``)."""
+        with torch.cuda.device(self.device):
+            check(lib().nr_plan_check(self._h, _stream(self.device)), "nr_plan_check")
+
     def info(self, index: int = 0) -> dict:
         buf = (ctypes.c_int64 * 8)()
         check(lib().nr_plan_info(self._h, index, buf, 8), "nr_plan_info")
