@@ -313,6 +313,25 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
                     const float* d_b, float* d_x, float* d_x_prev, float* d_y, float* d_grad,
                     float* d_scratch, double* d_state, nr_stream stream);
 
+/* mbir_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step, with the residual sinogram R y - b kept in a scratch array
+ * the library reserves on each device it runs on, NR_NOALLOC_SCRATCH_BYTES
+ * long, held until the process ends, instead of a caller's d_scratch.  The
+ * caller still passes every input, output and state buffer, and the plan
+ * must be bound.  Plans whose sinogram layout exceeds the array (max
+ * sino_off + n_angles*N_t floats above NR_NOALLOC_SCRATCH_BYTES/4) are refused
+ * with NR_INVALID_ARG before anything is enqueued.  The function itself
+ * allocates no device memory (the plan's own streams are created by its first
+ * multi-stream call of any entry point, as for mbir_step).  All calls on one
+ * device share the array: calls that overlap in time on one device (other
+ * streams, other threads) race and must be ordered by the caller; each call
+ * writes every scratch value it reads. */
+#define NR_NOALLOC_SCRATCH_BYTES (64u << 20)
+nr_status mbir_step_noalloc(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, const float* d_b,
+                            float* d_x, float* d_x_prev, float* d_y, float* d_grad, double* d_state,
+                            nr_stream stream);
+
 /* Resets an MBIR state (NR_MBIR_STATE_DOUBLES float64 on the device): t = 1,
  * every other entry 0.  Asynchronous on `stream`. */
 nr_status mbir_state_init(double* d_state, nr_stream stream);

@@ -86,6 +86,8 @@ SIGNATURES = {
                               c_void_p]),
     "mbir_step": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mbir_step_noalloc": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p]),
     "mbir_update": (c_int32, [POINTER(NrMbir), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                               c_void_p]),
     "mbir_state_init": (c_int32, [c_void_p, c_void_p]),

@@ -976,6 +976,56 @@ nr_status mbir_step(nr_plan* plan, const nr_prior* prior, const nr_mbir* params,
   return NR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// mbir_step without a caller scratch buffer: the residual sinogram lives in a
+// file-scope device array, one copy per device, reserved for the life of the
+// process.  Its device address comes from hipGetSymbolAddress with the device
+// current (the array's name is only a host-side stand-in in host code).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = NR_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+std::mutex g_scratch_mutex;
+std::vector<float*> g_scratch_ptr;   // per device, filled on first use
+
+nr_status scratch_for_current_device(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "mbir_step_noalloc: hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[size_t(dev)]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                 "mbir_step_noalloc: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[size_t(dev)] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_ptr[size_t(dev)];
+  return NR_OK;
+}
+
+}  // namespace
+
+nr_status mbir_step_noalloc(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, const float* d_b,
+                            float* d_x, float* d_x_prev, float* d_y, float* d_grad, double* d_state,
+                            nr_stream stream) {
+  if (!plan) return fail(NR_INVALID_ARG, "plan is NULL");
+  const size_t need = sino_extent(plan->p) * sizeof(float);
+  if (need > kNoAllocScratchBytes)
+    return fail(NR_INVALID_ARG, "mbir_step_noalloc: the plan's sinogram (" + std::to_string(need) +
+                                    " bytes) exceeds the library's scratch of " +
+                                    std::to_string(kNoAllocScratchBytes) + " bytes; use mbir_step");
+  if (nr_status st = check_bound(plan)) return st;
+  float* d_scratch = nullptr;
+  if (nr_status st = scratch_for_current_device(&d_scratch)) return st;
+  // every value of the scratch is written (R y - b) before it is read
+  return mbir_step(plan, prior, params, d_b, d_x, d_x_prev, d_y, d_grad, d_scratch, d_state, stream);
+}
+
 nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
                       int64_t count, double* d_state, nr_stream stream) {
   if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state)
