@@ -8,10 +8,12 @@ The data are the projector's own forward of the rasterised volume plus noise
 rows of that forward; one iteration at full size is checked against the same
 step composed from the separately verified entry points (forward, adjoint,
 prior gradient) in FP64 on the device; the 100 iterations are checked for a
-finite, decreasing objective whose data misfit comes down to the noise
-level.  The prior at lambda = 1 is weak against data of this scale, so the
-iterates fit noise late in the run (the reconstruction error is reported, and
-only required to beat the zero start).
+finite, decreasing objective, a data misfit at the noise level and a
+reconstruction error that falls.  lambda = 300: with lambda = 1 the prior is
+weak against data of this scale and the iterates fit the noise (error 0.35
+after 10 iterations, 0.49 after 100); at 300 the error falls through the
+whole run (0.83, 0.29, 0.16 after 10, 50, 100 iterations in a sweep of
+lambda in {1, 30, 300, 3000} on this stack).
 """
 
 import math
@@ -27,6 +29,7 @@ from oracle import radon as ora
 
 pytestmark = pytest.mark.gpu
 N, NZ, NA, ITERS = 2560, 128, 361, 100
+LAMBDA = 300.0
 SLICES = (37, 90)
 ANGLES = np.array([0, 200])
 
@@ -57,7 +60,7 @@ def problem():
     b_true = plan.fwd(vol)
     b = torch.as_tensor(synth.gaussian_noise(b_true, synth.rng_for(5, 2), 0.01), dtype=torch.float32,
                         device=dev).contiguous()
-    prior = Prior(lam=1.0)
+    prior = Prior(lam=LAMBDA)
     L = power_lipschitz(plan, 30) + prior.lipschitz()
     torch.cuda.synchronize()
     say(f"set-up {time.perf_counter() - t0:.1f} s, L = {L:.4g}")
@@ -123,15 +126,21 @@ def test_hundred_iterations(problem):
     torch.cuda.synchronize()
     e10, phi10 = err(m.x), objective(m.x)
     t0 = time.perf_counter()
-    m.run(ITERS - 10)
+    m.run(40)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    e50 = err(m.x)
+    t1 = time.perf_counter()
+    m.run(ITERS - 50)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) + (t1 - t0)
     e100, phi100, r100 = err(m.x), objective(m.x), misfit(m.x)
-    say(f"{ITERS} iterations: rel err {e10:.4f} (10) -> {e100:.4f} ({ITERS}); objective {phi0:.4g} -> "
-        f"{phi10:.4g} -> {phi100:.4g}; misfit / noise energy {r100 / noise:.3f}; "
+    say(f"{ITERS} iterations: rel err {e10:.4f} (10) -> {e50:.4f} (50) -> {e100:.4f} ({ITERS}); objective "
+        f"{phi0:.4g} -> {phi10:.4g} -> {phi100:.4g}; misfit / noise energy {r100 / noise:.3f}; "
         f"{(ITERS - 10) / dt:.2f} it/s; restarts {m.restarts}")
     assert not m.nonfinite
-    assert all(math.isfinite(v) for v in (e10, e100, phi10, phi100))
+    assert all(math.isfinite(v) for v in (e10, e50, e100, phi10, phi100))
     assert phi100 < phi10 < phi0
     assert r100 < 2.0 * noise
-    assert e10 < 1.0 and e100 < 1.0
+    # the error falls through the run and ends well below the start's
+    assert e100 <= e50 <= e10
+    assert e100 < 0.25
