@@ -827,14 +827,26 @@ nr_status radon_stream(nr_plan* plan, int32_t what, const nr_fbp* filter, const 
   if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_in, plan->io_fork, 0);
   if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_out, plan->io_fork, 0);
   if (e != hipSuccess) return hip_fail(e, "radon_stream set-up");
+  // copy in chunk i into buffer i & 1, which is free once the computation of
+  // chunk i - 2 is done
+  auto copy_in = [&](int64_t i) {
+    const int b = int(i & 1);
+    hipError_t ce = i >= 2 ? hipStreamWaitEvent(plan->io_in, plan->comp_done[b], 0) : hipSuccess;
+    if (ce == hipSuccess)
+      ce = hipMemcpyAsync(d_in[b], h_in + size_t(i) * n_in, n_in * sizeof(float), hipMemcpyHostToDevice,
+                          plan->io_in);
+    if (ce == hipSuccess) ce = hipEventRecord(plan->h2d_done[b], plan->io_in);
+    return ce;
+  };
+  e = copy_in(0);
+  if (e != hipSuccess) return hip_fail(e, "radon_stream copy in");
   for (int64_t i = 0; i < n_chunks; ++i) {
     const int b = int(i & 1);
-    // copy in: buffer b is free once the computation of chunk i-2 is done
-    if (i >= 2) e = hipStreamWaitEvent(plan->io_in, plan->comp_done[b], 0);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_in[b], h_in + size_t(i) * n_in, n_in * sizeof(float), hipMemcpyHostToDevice,
-                         plan->io_in);
-    if (e == hipSuccess) e = hipEventRecord(plan->h2d_done[b], plan->io_in);
+    // the next chunk's copy is enqueued before this chunk's computation and
+    // copy out: enqueueing a copy that waits on another stream's event can
+    // hold the host until that event completes, and the copy in of chunk
+    // i + 1 must not be enqueued only after the computation of chunk i
+    if (i + 1 < n_chunks) e = copy_in(i + 1);
     // compute: after its input arrived and chunk i-2's output left d_out[b]
     if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->h2d_done[b], 0);
     if (e == hipSuccess && i >= 2) e = hipStreamWaitEvent(st, plan->d2h_done[b], 0);

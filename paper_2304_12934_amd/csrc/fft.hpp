@@ -304,6 +304,30 @@ constexpr int tw_split(int R) {
   return b;
 }
 
+// w[r - 1] = tw[r st], r = 1..R-1 (w = tw[st] is e^{-2 pi i st/L}), as above
+template <int R>
+__device__ __forceinline__ void radix_twiddles(TwPtr __restrict__ tw, int st, float2 (&w)[R - 1]) {
+  if constexpr (R >= 8) {
+    constexpr int B = tw_split(R);
+    constexpr int A = (R - 1) / B + 1;
+    float2 lo[B], hi[A];
+    lo[1] = tw[st];
+    hi[1] = tw[B * st];
+#pragma unroll
+    for (int b = 2; b < B; ++b) lo[b] = c_mul(lo[b - 1], lo[1]);
+#pragma unroll
+    for (int a = 2; a < A; ++a) hi[a] = c_mul(hi[a - 1], hi[1]);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const int a = r / B, b = r % B;
+      w[r - 1] = a == 0 ? lo[b] : (b == 0 ? hi[a] : c_mul(hi[a], lo[b]));
+    }
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r - 1] = tw[r * st];
+  }
+}
+
 template <int L, int T, int P, bool INV>
 __device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) {
   constexpr int R = radix_of(L, P);
@@ -319,26 +343,7 @@ __device__ __forceinline__ void fft_pass(Lds s, TwPtr __restrict__ tw, int tid) 
     for (int i = 0; i < PER; ++i) {
       const int j = (NB % T == 0 || tid + i * T < NB) ? tid + i * T : 0;
       const int k = j % Ns;
-      const int st = k * (L / (Ns * R));
-      if constexpr (R >= 8) {
-        constexpr int B = tw_split(R);
-        constexpr int A = (R - 1) / B + 1;
-        float2 lo[B], hi[A];
-        lo[1] = tw[st];
-        hi[1] = tw[B * st];
-#pragma unroll
-        for (int b = 2; b < B; ++b) lo[b] = c_mul(lo[b - 1], lo[1]);
-#pragma unroll
-        for (int a = 2; a < A; ++a) hi[a] = c_mul(hi[a - 1], hi[1]);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const int a = r / B, b = r % B;
-          w[i][r - 1] = a == 0 ? lo[b] : (b == 0 ? hi[a] : c_mul(hi[a], lo[b]));
-        }
-      } else {
-#pragma unroll
-        for (int r = 1; r < R; ++r) w[i][r - 1] = tw[r * st];
-      }
+      radix_twiddles<R>(tw, k * (L / (Ns * R)), w[i]);
     }
   }
 #pragma unroll
@@ -449,14 +454,12 @@ __device__ __forceinline__ void fft_lds_store_out(Lds s, TwPtr __restrict__ tw, 
     // butterfly j of the last pass reads j + r Ns and yields outputs j + r Ns
     const int j = tid + i * T;
     if (Ns % T == 0 || j < Ns) {
-      float2 v[R];
+      float2 v[R], w[R - 1];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = s[j + r * Ns];
+      radix_twiddles<R>(tw, j, w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const float2 w = tw[r * j];
-        v[r] = c_mul(v[r], INV ? c_conj(w) : w);
-      }
+      for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], INV ? c_conj(w[r - 1]) : w[r - 1]);
       Dft<R, INV>::run(v);
 #pragma unroll
       for (int r = 0; r < R; ++r) {

@@ -209,7 +209,10 @@ __device__ __forceinline__ float block_max(float x, float* red, int tid) {
 template <int W>
 struct InterpLds {
   static constexpr int RW = kInterpTileW + W + 1, RH = kInterpTileH + W + 1;
-  static constexpr int RS = RW | 1;   // odd row stride of the planes
+  // staged from one cell before the region (an even grid column), in pairs
+  // of cells: RWP columns, an even count
+  static constexpr int RWP = (RW + 2) / 2 * 2;
+  static constexpr int RS = RWP | 1;   // odd row stride of the planes
 };
 template <int W, int TW, int TH>
 struct SpreadLds {
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
 template <int W, class LA, class KB>
 __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, float* reg_re, float* reg_im, const int tid) {
   constexpr int TW = kInterpTileW, TH = kInterpTileH;
-  constexpr int RW = InterpLds<W>::RW, RH = InterpLds<W>::RH, RS = InterpLds<W>::RS;
+  constexpr int RWP = InterpLds<W>::RWP, RH = InterpLds<W>::RH, RS = InterpLds<W>::RS;
   constexpr int T = 256, PER = kMaxChunk / T;
   const DSlice d = load_desc(a.descs + wi.slice);
   const SpreadItem it = d.iitems[wi.unit];
@@ -454,16 +457,22 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
     gy[k] = d.gxy[2 * ang + 1];
     fl[k] = d.flip[ang];
   }
-  const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 1;
-  const NR_G float2* __restrict__ ext = d.ext;
+  // the region's first row and (even) first column: one cell before the
+  // tile's margin, so that every 16-byte load takes two cells of a row (grid
+  // rows are 64-byte aligned and hold an even number of cells)
+  const int r0 = (it.tile / d.itiles_x) * TH - 1, c0 = (it.tile % d.itiles_x) * TW - 2;
+  const NR_G float4* __restrict__ ext4 = reinterpret_cast<const NR_G float4*>(d.ext);
   // staged cells off the grid are never read by a point: clamp the address, keep the load unconditional
-  NR_STRIDED(c, RH * RW, T) {
-    const int rl = c / RW, cl = c % RW;
+  constexpr int PAIRS = RWP / 2;
+  NR_STRIDED(c, RH * PAIRS, T) {
+    const int rl = c / PAIRS, pl = c % PAIRS;
     const int r = min(max(r0 + rl, 0), d.rows - 1);
-    const int cc = min(max(c0 + cl, 0), d.cols - 1);
-    const float2 v = ext[size_t(r) * d.cols + cc];
-    reg_re[rl * RS + cl] = v.x;
-    reg_im[rl * RS + cl] = v.y;
+    const int cc = min(max(c0 + 2 * pl, 0), d.cols - 2);
+    const float4 v = ext4[(size_t(r) * d.cols + cc) >> 1];
+    reg_re[rl * RS + 2 * pl] = v.x;
+    reg_im[rl * RS + 2 * pl] = v.y;
+    reg_re[rl * RS + 2 * pl + 1] = v.z;
+    reg_im[rl * RS + 2 * pl + 1] = v.w;
   }
   __syncthreads();
   const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
