@@ -318,13 +318,31 @@ __device__ __forceinline__ void fwd_cols_unit(const LA& a, const WorkItem wi, fl
   const int lim = r2 <= 0 ? -1 : int(sqrtf(float(r2)));
   const bool full = lim >= L / 2;   // the whole row, q_y = -L/2 included
   const int cnt = full ? L : 2 * lim + 1;
-  for (int k = tid; k < cnt; k += T) {
-    const int n = (full || k <= lim) ? k : L - cnt + k;
-    const float2 v = s[n];
-    store_row<L>(row, colpad, n, v);
-    const int nm = n == 0 ? 0 : L - n;
-    if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
-    if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+  if (m1 || m2) {   // the few columns next to qx = 0 and G/2 also fill mirror rows
+    for (int k = tid; k < cnt; k += T) {
+      const int n = (full || k <= lim) ? k : L - cnt + k;
+      const float2 v = s[n];
+      store_row<L>(row, colpad, n, v);
+      const int nm = n == 0 ? 0 : L - n;
+      if (m1) store_row<L>(m1, colpad, nm, c_conj(v));
+      if (m2) store_row<L>(m2, colpad, nm, c_conj(v));
+    }
+  } else {
+    // the kept natural indices are one contiguous run of row positions
+    // m = (n + L/2) mod L: [L/2 - lim, L/2 + lim], or the whole row
+    const int m0 = full ? 0 : L / 2 - lim;
+    NR_G float2* __restrict__ out = row + colpad + m0;
+#pragma unroll 4
+    for (int k = tid; k < cnt; k += T) {
+      const int m = m0 + k;
+      out[k] = s[m < L / 2 ? m + L / 2 : m - L / 2];
+    }
+    // periodic copies: positions m in [L - colpad, L) also at m - L (left
+    // pad), m in [0, colpad) also at m + L (right pad), when stored
+    if (tid < 2 * colpad) {
+      const int m = tid < colpad ? tid + L - colpad : tid - colpad;
+      if (m >= m0 && m < m0 + cnt) row[tid < colpad ? tid : L + tid] = s[m < L / 2 ? m + L / 2 : m - L / 2];
+    }
   }
   __syncthreads();
 }
@@ -860,15 +878,29 @@ __device__ __forceinline__ void adj_cols_unit(const LA& a, const WorkItem wi, fl
   // than rdisc from the origin (nor onto any copy of such a cell), so those
   // cells are zero and not read.
   const int r2 = d.rdisc * d.rdisc - qx * qx;
-  fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
-    const int qy = n < L / 2 ? n : n - L;
-    if (qy * qy > r2) return make_float2(0.f, 0.f);
-    float2 v = load_folded<L>(row, colpad, n);
-    const int nm = n == 0 ? 0 : L - n;
-    if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
-    if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
-    return v;
-  });
+  // Cells with |q_y| >= L/2 - colpad have periodic copies to fold in; a
+  // column whose disc stops short of them, and that has no mirror rows (all
+  // but a few), reads each cell once.
+  const int lim = r2 < 0 ? -1 : int(sqrtf(float(r2)));
+  if (m1 || m2 || lim >= L / 2 - colpad) {
+    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+      const int qy = n < L / 2 ? n : n - L;
+      if (qy * qy > r2) return make_float2(0.f, 0.f);
+      float2 v = load_folded<L>(row, colpad, n);
+      const int nm = n == 0 ? 0 : L - n;
+      if (m1) v = c_add(v, c_conj(load_folded<L>(m1, colpad, nm)));
+      if (m2) v = c_add(v, c_conj(load_folded<L>(m2, colpad, nm)));
+      return v;
+    });
+  } else {
+    const NR_G float2* __restrict__ mid = row + colpad + L / 2;   // the cell of q_y = 0
+    fft_first_pass_from<L, T, true, false>(s, tid, [&](int n) {
+      const int qy = n < L / 2 ? n : n - L;
+      if (qy * qy > r2) return make_float2(0.f, 0.f);
+      const float2 v = mid[qy];
+      return v;
+    });
+  }
   // only y = iy - N/2 in [-N/2, N/2) is kept: natural indices [0, N/2) and
   // [L - N/2, L); row iy of column qx is half iy & 1 of tile entry t4(qx, iy / 2)
   NR_G float2* __restrict__ T2 = (NR_G float2*)d.T;
