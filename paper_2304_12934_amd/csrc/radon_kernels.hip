@@ -212,7 +212,7 @@ struct InterpLds {
   // staged from one cell before the region (an even grid column), in pairs
   // of cells: RWP columns, an even count
   static constexpr int RWP = (RW + 2) / 2 * 2;
-  static constexpr int RS = RWP | 1;   // odd row stride of the planes
+  static constexpr int RS = RWP | 1;   // odd row stride (in complex cells)
 };
 template <int W, int TW, int TH>
 struct SpreadLds {
@@ -447,12 +447,12 @@ __global__ __launch_bounds__(fft_threads(L)) void k_fwd_interp(LaunchArgs a, KBA
 // W-1 cells the footprints reach past it and a one-cell margin on each side,
 // then every thread interpolates its points from LDS (the same sums, in the
 // same order, as interp_point) into the half-line buffer yh, scaled by 1/N_t.
-// The staged cells are split into a real and an imaginary plane with an odd
-// row stride: neighbouring lanes take neighbouring points of one line, about
-// two cells apart, and an even stride (interleaved complex values) put them
-// on a few LDS banks.
+// The staged cells are complex values with an odd row stride (neighbouring
+// lanes take neighbouring points of one line, about two cells apart): a
+// point's taps along a row are read two cells per LDS instruction, which
+// measured 2 % faster than separate real and imaginary planes.
 template <int W, class LA, class KB>
-__device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, float* reg_re, float* reg_im, const int tid) {
+__device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, float2* reg, const int tid) {
   constexpr int TW = kInterpTileW, TH = kInterpTileH;
   constexpr int RWP = InterpLds<W>::RWP, RH = InterpLds<W>::RH, RS = InterpLds<W>::RS;
   constexpr int T = 256, PER = kMaxChunk / T;
@@ -487,10 +487,8 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
     const int r = min(max(r0 + rl, 0), d.rows - 1);
     const int cc = min(max(c0 + 2 * pl, 0), d.cols - 2);
     const float4 v = ext4[(size_t(r) * d.cols + cc) >> 1];
-    reg_re[rl * RS + 2 * pl] = v.x;
-    reg_im[rl * RS + 2 * pl] = v.y;
-    reg_re[rl * RS + 2 * pl + 1] = v.z;
-    reg_im[rl * RS + 2 * pl + 1] = v.w;
+    reg[rl * RS + 2 * pl] = make_float2(v.x, v.y);
+    reg[rl * RS + 2 * pl + 1] = make_float2(v.z, v.w);
   }
   __syncthreads();
   const int rb = a.halo - r0, cb = d.G / 2 + a.colpad - c0;
@@ -512,7 +510,7 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
       float2 r = make_float2(0.f, 0.f);
 #pragma unroll
       for (int l = 0; l < W; ++l) {
-        const float2 v = make_float2(reg_re[o + i * RS + l], reg_im[o + i * RS + l]);
+        const float2 v = reg[o + i * RS + l];
         r.x = fmaf(wy[l], v.x, r.x);
         r.y = fmaf(wy[l], v.y, r.y);
       }
@@ -526,9 +524,8 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
 
 template <int W>
 __global__ __launch_bounds__(256) void k_interp_tiles(LaunchArgs a, KBArgs kb) {
-  __shared__ float reg_re[InterpLds<W>::RH * InterpLds<W>::RS];
-  __shared__ float reg_im[InterpLds<W>::RH * InterpLds<W>::RS];
-  NR_FOR_EACH_UNIT(a, wi) interp_tiles_unit<W>(a, kb, wi, reg_re, reg_im, int(threadIdx.x));
+  __shared__ float2 reg[InterpLds<W>::RH * InterpLds<W>::RS];
+  NR_FOR_EACH_UNIT(a, wi) interp_tiles_unit<W>(a, kb, wi, reg, int(threadIdx.x));
 }
 
 // F4 after k_interp_tiles: per pair of angles, the Hermitian completions of
@@ -989,7 +986,7 @@ template <int W>
 struct PersistLds {
   static constexpr int FFT = 4096 * int(sizeof(float2));
   static constexpr int SPREAD = 2 * SpreadLds<W, 64, 32>::AH * SpreadLds<W, 64, 32>::TS * int(sizeof(int));
-  static constexpr int INTERP = 2 * InterpLds<W>::RH * InterpLds<W>::RS * int(sizeof(float));
+  static constexpr int INTERP = InterpLds<W>::RH * InterpLds<W>::RS * int(sizeof(float2));
   static constexpr int BYTES = FFT > SPREAD ? (FFT > INTERP ? FFT : INTERP) : (SPREAD > INTERP ? SPREAD : INTERP);
 };
 
@@ -1022,8 +1019,7 @@ __device__ __forceinline__ void persist_unit(const LA& a, const KB& kb, int stag
       }
       return;
     case StageKind::FwdInterp: {
-      float* re = reinterpret_cast<float*>(lds);
-      interp_tiles_unit<W>(a, kb, wi, re, re + InterpLds<W>::RH * InterpLds<W>::RS, tid);
+      interp_tiles_unit<W>(a, kb, wi, reinterpret_cast<float2*>(lds), tid);
       return;
     }
     case StageKind::FwdRadial:
