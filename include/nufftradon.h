@@ -332,6 +332,34 @@ nr_status mbir_step_noalloc(nr_plan* plan, const nr_prior* prior, const nr_mbir*
                             float* d_x, float* d_x_prev, float* d_y, float* d_grad, double* d_state,
                             nr_stream stream);
 
+/* One step of mbir_step's iteration over a volume that lives in host memory
+ * (Sec. 4.1, the partition along the rotation axis streamed through the GPU):
+ * the plan describes one chunk of nz uniform slices (shared N, angles and
+ * bins, vol_off = z*N*N, sino_off = z*n_angles*n_det) and the volume is
+ * n_chunks such chunks, Z = n_chunks*nz slices, stacked in order.
+ * h_x = x_k and h_x_prev = x_{k-1} ([Z][N][N] float32, host), h_b the data
+ * (n_chunks copies of the plan's sinogram layout back to back, host);
+ * h_x_next (host, not aliasing the inputs) receives x_{k+1}.  The
+ * extrapolated point y_k = x_k + beta (x_k - x_{k-1}) is formed on the device
+ * per chunk (beta from d_state, set by the previous call's restart test;
+ * mbir_state_init gives beta = 0, so the first call takes y_0 = x_0 with any
+ * h_x_prev), with one halo slice each side for the prior; the gradient, x_{k+1}
+ * = y_k - g/L (clamped when nonneg) and the restart dot product follow chunk
+ * by chunk, and after the last chunk the restart test, t and beta as in
+ * mbir_step.  The iterates equal mbir_step's over the whole volume up to
+ * float32 rounding.  Chunk c + 1 is copied in on a plan-owned stream while
+ * chunk c is computed on `stream` and chunk c - 1 copied out on another;
+ * pinned host buffers let the copies overlap.  d_work: device work area of
+ * mbir_stream_work_bytes bytes (two input sets of 2(nz + 2) slices and one
+ * chunk of data, the extended y and prior gradient, the gradient, the
+ * residual and two output chunks).  Non-monotone steps only (monotone = 1 is
+ * NR_INVALID_ARG).  Asynchronous on `stream`: h_x_next is complete once
+ * `stream` has reached this point. */
+nr_status mbir_stream_work_bytes(const nr_plan* plan, size_t* bytes);
+nr_status mbir_stream_iterate(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, int64_t n_chunks,
+                              const float* h_b, const float* h_x, const float* h_x_prev, float* h_x_next,
+                              void* d_work, size_t work_bytes, double* d_state, nr_stream stream);
+
 /* Resets an MBIR state (NR_MBIR_STATE_DOUBLES float64 on the device): t = 1,
  * every other entry 0.  Asynchronous on `stream`. */
 nr_status mbir_state_init(double* d_state, nr_stream stream);

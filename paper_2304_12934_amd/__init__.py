@@ -8,6 +8,7 @@ from .radon import (  # noqa: F401
     MBIR,
     DataFidelityFn,
     Graph,
+    HostMBIR,
     Plan,
     Prior,
     QGGMRFFn,
@@ -19,5 +20,5 @@ from .radon import (  # noqa: F401
     stream_stack,
 )
 
-__all__ = ["Plan", "Graph", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "qggmrf_grad",
-           "power_lipschitz", "kb_eval", "stream_stack"]
+__all__ = ["Plan", "Graph", "SliceGeometry", "Prior", "RadonFn", "DataFidelityFn", "QGGMRFFn", "MBIR", "HostMBIR",
+           "qggmrf_grad", "power_lipschitz", "kb_eval", "stream_stack"]

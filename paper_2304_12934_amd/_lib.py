@@ -90,6 +90,9 @@ SIGNATURES = {
                                     c_void_p, c_void_p, c_void_p, c_void_p]),
     "mbir_update": (c_int32, [POINTER(NrMbir), c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                               c_void_p]),
+    "mbir_stream_work_bytes": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "mbir_stream_iterate": (c_int32, [c_void_p, POINTER(NrPrior), POINTER(NrMbir), c_int64, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "mbir_state_init": (c_int32, [c_void_p, c_void_p]),
     "nr_prior_init": (c_int32, [POINTER(NrPrior), c_float, c_float, c_float, c_float, c_int32]),
     "nr_prior_lipschitz": (c_int32, [POINTER(NrPrior), POINTER(c_double)]),

@@ -1038,6 +1038,159 @@ nr_status mbir_step_noalloc(nr_plan* plan, const nr_prior* prior, const nr_mbir*
   return mbir_step(plan, prior, params, d_b, d_x, d_x_prev, d_y, d_grad, d_scratch, d_state, stream);
 }
 
+namespace {
+
+// Device work area of mbir_stream_iterate for a plan of nz uniform slices:
+// two input sets (x_k and x_{k-1} with one halo slice each side, and the
+// chunk's data), then y and the prior's gradient over the halo-extended
+// chunk, the data-term gradient, the residual and two output chunks.
+struct StreamMbirLayout {
+  size_t ext, vol, sino;                    // float counts
+  size_t xk[2], xp[2], b[2], y, gp, g, r, out[2], bytes;   // byte offsets, total
+};
+
+nr_status stream_mbir_layout(const nr::Plan& p, StreamMbirLayout& L) {
+  if (p.slices.empty()) return fail(NR_INVALID_ARG, "mbir_stream: empty plan");
+  const nr_slice& s0 = p.slices[0];
+  const int64_t n = s0.n, per_sino = int64_t(s0.n_angles) * s0.n_det;
+  for (size_t z = 0; z < p.slices.size(); ++z) {
+    const nr_slice& sl = p.slices[z];
+    if (sl.n != s0.n || sl.n_angles != s0.n_angles || sl.n_det != s0.n_det || sl.vol_off != int64_t(z) * n * n ||
+        sl.sino_off != int64_t(z) * per_sino)
+      return fail(NR_INVALID_ARG,
+                  "mbir_stream: the plan's slices must share N, angles and bins and sit at vol_off = z*N*N, "
+                  "sino_off = z*n_angles*n_det");
+  }
+  const size_t nz = p.slices.size();
+  L.vol = nz * size_t(n) * size_t(n);
+  L.ext = (nz + 2) * size_t(n) * size_t(n);
+  L.sino = nz * size_t(per_sino);
+  size_t off = 0;
+  auto take = [&](size_t floats) {
+    const size_t o = off;
+    off = align256(off + floats * sizeof(float));
+    return o;
+  };
+  for (int k = 0; k < 2; ++k) {
+    L.xk[k] = take(L.ext);
+    L.xp[k] = take(L.ext);
+    L.b[k] = take(L.sino);
+  }
+  L.y = take(L.ext);
+  L.gp = take(L.ext);
+  L.g = take(L.vol);
+  L.r = take(L.sino);
+  L.out[0] = take(L.vol);
+  L.out[1] = take(L.vol);
+  L.bytes = off;
+  return NR_OK;
+}
+
+}  // namespace
+
+nr_status mbir_stream_work_bytes(const nr_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(NR_INVALID_ARG, "mbir_stream_work_bytes: NULL argument");
+  StreamMbirLayout L{};
+  if (nr_status st = stream_mbir_layout(plan->p, L)) return st;
+  *bytes = L.bytes;
+  return NR_OK;
+}
+
+nr_status mbir_stream_iterate(nr_plan* plan, const nr_prior* prior, const nr_mbir* params, int64_t n_chunks,
+                              const float* h_b, const float* h_x, const float* h_x_prev, float* h_x_next,
+                              void* d_work, size_t work_bytes, double* d_state, nr_stream stream) {
+  if (nr_status st = check_bound(plan)) return st;
+  if (!params || !h_b || !h_x || !h_x_prev || !h_x_next || !d_work || !d_state)
+    return fail(NR_INVALID_ARG, "mbir_stream_iterate: NULL argument");
+  if (n_chunks < 1) return fail(NR_INVALID_ARG, "mbir_stream_iterate: n_chunks < 1");
+  if (nr_status st = check_prior(prior)) return st;
+  if (nr_status st = check_mbir(params)) return st;
+  if (params->monotone) return fail(NR_INVALID_ARG, "mbir_stream_iterate: the monotone step is not supported");
+  if (h_x_next == h_x || h_x_next == h_x_prev)
+    return fail(NR_INVALID_ARG, "mbir_stream_iterate: h_x_next must not alias h_x or h_x_prev");
+  const nr::Plan& p = plan->p;
+  StreamMbirLayout L{};
+  if (nr_status st = stream_mbir_layout(p, L)) return st;
+  if (work_bytes < L.bytes) return fail(NR_WORKSPACE_TOO_SMALL, "mbir_stream_iterate: work area too small");
+  if (nr_status st = pending_error("before mbir_stream_iterate")) return st;
+  const int n = p.slices[0].n;
+  const size_t slice = size_t(n) * size_t(n);
+  const int64_t nz = int64_t(p.slices.size()), Z = nz * n_chunks;
+  char* w = static_cast<char*>(d_work);
+  auto F = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const nrk::PriorArgs pa = prior_args(prior);
+  const bool prior_on = prior->lambda > 0.0f;
+  hipError_t e = ensure_io(plan);
+  // the step's dot product accumulates over the chunks from zero
+  if (e == hipSuccess) e = nrk::launch_set_double(d_state + nrk::kStDot, 0.0, st);
+  if (e == hipSuccess) e = hipEventRecord(plan->io_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_in, plan->io_fork, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_out, plan->io_fork, 0);
+  if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate set-up");
+  // chunk c holds slices [c nz, (c+1) nz); its input buffers hold slices
+  // [c nz - 1, (c+1) nz + 1) clipped to the volume, slice c nz - 1 at index 0
+  auto lo = [&](int64_t c) { return std::max<int64_t>(c * nz - 1, 0); };
+  auto hi = [&](int64_t c) { return std::min<int64_t>((c + 1) * nz + 1, Z); };
+  auto copy_in = [&](int64_t c) {
+    const int k = int(c & 1);
+    const int64_t z0 = lo(c), z1 = hi(c);
+    const size_t first = size_t(z0 - (c * nz - 1)) * slice, count = size_t(z1 - z0) * slice;
+    hipError_t ce = c >= 2 ? hipStreamWaitEvent(plan->io_in, plan->comp_done[k], 0) : hipSuccess;
+    if (ce == hipSuccess)
+      ce = hipMemcpyAsync(F(L.xk[k]) + first, h_x + size_t(z0) * slice, count * sizeof(float),
+                          hipMemcpyHostToDevice, plan->io_in);
+    if (ce == hipSuccess)
+      ce = hipMemcpyAsync(F(L.xp[k]) + first, h_x_prev + size_t(z0) * slice, count * sizeof(float),
+                          hipMemcpyHostToDevice, plan->io_in);
+    if (ce == hipSuccess)
+      ce = hipMemcpyAsync(F(L.b[k]), h_b + size_t(c) * L.sino, L.sino * sizeof(float), hipMemcpyHostToDevice,
+                          plan->io_in);
+    if (ce == hipSuccess) ce = hipEventRecord(plan->h2d_done[k], plan->io_in);
+    return ce;
+  };
+  e = copy_in(0);
+  if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate copy in");
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const int k = int(c & 1);
+    // the next chunk's copy in goes ahead of this chunk's work (see radon_stream)
+    if (c + 1 < n_chunks) e = copy_in(c + 1);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->h2d_done[k], 0);
+    // output buffer k is free once chunk c - 2 has been copied out
+    if (e == hipSuccess && c >= 2) e = hipStreamWaitEvent(st, plan->d2h_done[k], 0);
+    if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate copy in");
+    const int64_t z0 = lo(c), z1 = hi(c);
+    const size_t first = size_t(z0 - (c * nz - 1)) * slice, count = size_t(z1 - z0) * slice;
+    // y = x_k + beta (x_k - x_{k-1}) over the chunk and its halo slices
+    e = nrk::launch_mbir_extrapolate(F(L.y) + first, F(L.xk[k]) + first, F(L.xp[k]) + first, count, d_state, st);
+    // the prior's gradient over the extended chunk (its halo slices' own
+    // values are wrong, missing their outer neighbours, and unused)
+    if (e == hipSuccess && prior_on)
+      e = nrk::launch_qggmrf(F(L.y) + first, F(L.gp) + first, nullptr, int(z1 - z0), n, pa, 1.0f, st, false);
+    if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate prior");
+    // R^T (R y - b) over the chunk's own slices
+    if (nr_status s = radon_normal(plan, F(L.y) + slice, F(L.b[k]), F(L.r), F(L.g), stream)) return s;
+    // x_{k+1} = y - g/L and the restart test's dot product
+    e = nrk::launch_mbir_dot_accumulate(F(L.xk[k]) + slice, F(L.y) + slice, F(L.g),
+                                        prior_on ? F(L.gp) + slice : nullptr, L.vol, params->inv_L, params->nonneg,
+                                        d_state, F(L.out[k]), st);
+    if (e == hipSuccess) e = hipEventRecord(plan->comp_done[k], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->io_out, plan->comp_done[k], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_x_next + size_t(c) * L.vol, F(L.out[k]), L.vol * sizeof(float), hipMemcpyDeviceToHost,
+                         plan->io_out);
+    if (e == hipSuccess) e = hipEventRecord(plan->d2h_done[k], plan->io_out);
+    if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate chunk");
+  }
+  // restart test and momentum for the next step, then the caller's stream
+  // waits for the last copy out
+  e = nrk::launch_mbir_finalize(d_state, params->restart, st);
+  if (e == hipSuccess) e = hipEventRecord(plan->io_done, plan->io_out);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->io_done, 0);
+  if (e != hipSuccess) return hip_fail(e, "mbir_stream_iterate join");
+  return NR_OK;
+}
+
 nr_status mbir_update(const nr_mbir* params, float* d_x, float* d_x_prev, float* d_y, const float* d_grad,
                       int64_t count, double* d_state, nr_stream stream) {
   if (!params || !d_x || !d_x_prev || !d_y || !d_grad || !d_state)

@@ -573,6 +573,37 @@ hipError_t launch_mbir_finish_monotone(float* x, float* x_prev, float* y, size_t
   return hipGetLastError();
 }
 
+// y = x + beta (x - x_prev) with the beta of the last finalised step: the
+// extrapolated point of the accelerated-gradient iteration, formed when the
+// iterates live elsewhere (host memory) and only x and x_prev are kept
+__global__ __launch_bounds__(256) void k_mbir_extrapolate(float* __restrict__ y, const float* __restrict__ x,
+                                                          const float* __restrict__ x_prev, size_t count,
+                                                          const double* __restrict__ state) {
+  const float beta = float(state[kStBeta]);
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) {
+    const float xn = x[i];
+    y[i] = xn + beta * (xn - x_prev[i]);
+  }
+}
+
+hipError_t launch_mbir_extrapolate(float* y, const float* x, const float* x_prev, size_t count, const double* state,
+                                   hipStream_t st) {
+  const size_t blocks = std::min<size_t>(4096, std::max<size_t>(1, (count + 255) / 256));
+  hipLaunchKernelGGL(k_mbir_extrapolate, dim3(unsigned(blocks)), dim3(256), 0, st, y, x, x_prev, count, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbir_dot_accumulate(const float* x, const float* y, float* g, const float* gp, size_t count,
+                                      float inv_L, int nonneg, double* state, float* cand, hipStream_t st) {
+  hipLaunchKernelGGL(k_mbir_dot, dim3(2048), dim3(256), 0, st, x, y, g, count, inv_L, nonneg, state, cand, gp);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbir_finalize(double* state, int restart, hipStream_t st) {
+  hipLaunchKernelGGL(k_mbir_finalize, dim3(1), dim3(1), 0, st, state, restart, 0);
+  return hipGetLastError();
+}
+
 __global__ void k_mbir_state_init(double* state) {
   if (threadIdx.x < kStCount) state[threadIdx.x] = threadIdx.x == kStT ? 1.0 : 0.0;
 }

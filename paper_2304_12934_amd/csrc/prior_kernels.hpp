@@ -51,6 +51,15 @@ hipError_t launch_mbir_finish_monotone(float* x, float* x_prev, float* y, size_t
                                        hipStream_t st);
 // t = 1, every other slot 0
 hipError_t launch_mbir_state_init(double* state, hipStream_t st);
+// y = x + beta (x - x_prev), beta from the state (the last finalised step)
+hipError_t launch_mbir_extrapolate(float* y, const float* x, const float* x_prev, size_t count, const double* state,
+                                   hipStream_t st);
+// state's <g, x' - x> += that of these elements, with g <- g + gp when gp
+// is given and x' = y - g/L (clamped when nonneg) stored into cand
+hipError_t launch_mbir_dot_accumulate(const float* x, const float* y, float* g, const float* gp, size_t count,
+                                      float inv_L, int nonneg, double* state, float* cand, hipStream_t st);
+// restart test on the accumulated dot product, then t and beta
+hipError_t launch_mbir_finalize(double* state, int restart, hipStream_t st);
 // v[i] = uniform in [-1, 1) from (seed, first + i); v[i] = value
 hipError_t launch_fill_random(float* v, size_t count, uint64_t seed, uint64_t first, hipStream_t st);
 hipError_t launch_fill_value(float* v, size_t count, float value, hipStream_t st);

@@ -618,6 +618,100 @@ class MBIR:
         return float(st[0]) if float(st[1]) != 0.0 else float("nan")
 
 
+class HostMBIR:
+    """Accelerated-gradient MBIR over a volume in host memory (Sec. 4.1: the
+    partition along the rotation axis streamed through the GPU): one
+    ``mbir_stream_iterate`` per iteration.  ``plan`` describes one chunk of
+    slices; the volume is ``n_chunks`` chunks stacked in order, and ``b_host``
+    their data back to back.  The iterates x_k, x_{k-1} and x_{k+1} live in
+    three pinned host buffers that rotate each step; the device holds two
+    chunks in flight.  Steps match ``MBIR.step`` (non-monotone) up to float32
+    rounding.  ``L``/``L_data`` as for ``MBIR`` (a chunk's power iteration
+    gives the volume's ``L_data``: ``R^T R`` acts slice by slice)."""
+
+    def __init__(self, plan: Plan, b_host: torch.Tensor, n_chunks: int, prior: Prior, L: float | None = None,
+                 nonneg: bool = False, x0: torch.Tensor | None = None, L_data: float | None = None,
+                 restart: bool = True):
+        if not plan.uniform:
+            raise ValueError("HostMBIR needs a uniform stack (one N for every slice)")
+        if n_chunks < 1:
+            raise ValueError("n_chunks must be >= 1")
+        if (b_host.device.type != "cpu" or b_host.dtype != torch.float32 or not b_host.is_contiguous()
+                or b_host.numel() != n_chunks * plan.sino_numel):
+            raise ValueError(f"b_host must be a contiguous float32 CPU tensor of {n_chunks * plan.sino_numel} "
+                             "elements")
+        self.plan, self.prior, self.n_chunks = plan, prior, int(n_chunks)
+        self.b = b_host
+        nz, n = plan.vol_shape()[0], plan.vol_shape()[1]
+        shape = (self.n_chunks * nz, n, n)
+        bufs = [torch.zeros(shape, dtype=torch.float32, pin_memory=True) for _ in range(3)]
+        if x0 is not None:
+            bufs[0].copy_(x0.reshape(shape))
+        bufs[1].copy_(bufs[0])
+        self._x, self._x_prev, self._x_next = bufs
+        size = ctypes.c_size_t()
+        check(lib().mbir_stream_work_bytes(plan._h, ctypes.byref(size)), "mbir_stream_work_bytes")
+        dev = plan.device
+        self.work = torch.empty(max(1, size.value), dtype=torch.uint8, device=dev)
+        self.state = torch.empty(NR_MBIR_STATE_DOUBLES, dtype=torch.float64, device=dev)
+        with torch.cuda.device(dev):
+            check(lib().mbir_state_init(_ptr(self.state), _stream(dev)), "mbir_state_init")
+        self._prior_c = prior.as_c()
+        self.params = NrMbir()
+        flags = (1 if restart else 0, 1 if nonneg else 0, 0)
+        if L is not None:
+            check(lib().nr_mbir_params(float(L), None, *flags, ctypes.byref(self.params)), "nr_mbir_params")
+        else:
+            ld = power_lipschitz(plan) if L_data is None else float(L_data)
+            check(lib().nr_mbir_params(ld, ctypes.byref(self._prior_c), *flags, ctypes.byref(self.params)),
+                  "nr_mbir_params")
+        self.k = 0
+
+    def step(self) -> None:
+        """Enqueue one iteration; the host buffers must not be touched until
+        the plan's device stream is synchronised (``x`` does that)."""
+        dev = self.plan.device
+        with torch.cuda.device(dev):
+            check(lib().mbir_stream_iterate(self.plan._h, ctypes.byref(self._prior_c), ctypes.byref(self.params),
+                                            self.n_chunks, _ptr(self.b), _ptr(self._x), _ptr(self._x_prev),
+                                            _ptr(self._x_next), _ptr(self.work), self.work.numel(),
+                                            _ptr(self.state), _stream(dev)), "mbir_stream_iterate")
+        self._x_prev, self._x, self._x_next = self._x, self._x_next, self._x_prev
+        self.k += 1
+
+    def run(self, iters: int) -> torch.Tensor:
+        for _ in range(iters):
+            self.step()
+        return self.x
+
+    def reset(self, x0: torch.Tensor | None = None) -> None:
+        """Start again from ``x0`` (zeros when None) with a fresh state."""
+        dev = self.plan.device
+        torch.cuda.current_stream(dev).synchronize()
+        if x0 is None:
+            self._x.zero_()
+        else:
+            self._x.copy_(x0.reshape(self._x.shape))
+        self._x_prev.copy_(self._x)
+        with torch.cuda.device(dev):
+            check(lib().mbir_state_init(_ptr(self.state), _stream(dev)), "mbir_state_init")
+        self.k = 0
+
+    @property
+    def x(self) -> torch.Tensor:
+        """The current iterate (host, pinned), after synchronising the stream."""
+        torch.cuda.current_stream(self.plan.device).synchronize()
+        return self._x
+
+    @property
+    def restarts(self) -> int:
+        return int(self.state[3].item())
+
+    @property
+    def nonfinite(self) -> bool:
+        return bool(self.state[2].item() != 0.0)
+
+
 def stream_stack(what: str, host_in: torch.Tensor, n: int, n_det: int, angles, chunk: int, center: float = 0.0,
                  device: torch.device | str | None = None, filter: str = "ramp", order: int = 2,
                  cutoff: float = 0.25, tuning: dict | None = None) -> torch.Tensor:

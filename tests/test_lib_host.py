@@ -208,3 +208,28 @@ def test_autotune_scratch_and_tuning_keys(L):
                 assert ws.value + 2 * 4 * (128 * 128 + 64 * 64) + 4 * 40 * 192 <= need.value
     # without a device the tuner itself stops at its first HIP call with a status, not a crash
     L.nr_plan_destroy(h)
+
+
+def test_host_mbir_work_area(L):
+    """mbir_stream_work_bytes: two input sets of 2 (nz + 2) slices and one chunk
+    of data, the extended y and prior gradient, the gradient, the residual and
+    two output chunks, each 256-byte aligned; uneven plans are refused."""
+    from paper_2304_12934_amd import _lib
+    n, na, nz = 128, 90, 3
+    ang = np.linspace(0, np.pi, na, endpoint=False)
+    st, h = _create(L, [(n, n, na, z * n * n, z * na * n, 0) for z in range(nz)], ang)
+    assert st == _lib.NR_OK
+    got = ctypes.c_size_t()
+    assert L.mbir_stream_work_bytes(h, ctypes.byref(got)) == _lib.NR_OK
+
+    def a(v):
+        return (v + 255) // 256 * 256
+
+    ext, vol, sino = 4 * (nz + 2) * n * n, 4 * nz * n * n, 4 * nz * na * n
+    assert got.value == 2 * (2 * a(ext) + a(sino)) + 2 * a(ext) + a(vol) + a(sino) + 2 * a(vol)
+    assert L.mbir_stream_work_bytes(h, None) == _lib.NR_INVALID_ARG
+    L.nr_plan_destroy(h)
+    st, h = _create(L, [(n, n, na, 0, 0, 0), (64, 64, na, n * n, na * n, 0)], ang)
+    assert st == _lib.NR_OK
+    assert L.mbir_stream_work_bytes(h, ctypes.byref(got)) == _lib.NR_INVALID_ARG
+    L.nr_plan_destroy(h)
