@@ -315,8 +315,68 @@ def config5_leg(dev, iters: int = 100) -> dict:
            "iterations": iters, "lambda": CONFIG5_LAMBDA, "iters_per_s": round(ips, 2),
            "model_GB_per_iter": round(gb, 2), "frac_of_hbm_peak": round(gb * ips / HBM_PEAK_GBS, 4),
            "recon_rel_err_10": round(e10, 4), "recon_rel_err_final": round(err(m.x), 4), "restarts": m.restarts}
+    del m
+    torch.cuda.empty_cache()
+    out["host_resident"] = host_mbir_leg(dev, plan, b, prior, L_data, n, nz, na)
     plan.close()
-    del m, vol, b
+    del vol, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_mbir_leg(dev, plan, b, prior, L_data: float, n: int, nz: int, na: int, chunk: int = 16,
+                  iters: int = 3) -> dict:
+    """The sparse-view workload with its iterates in host memory (pinned):
+    mbir_stream_iterate streams chunks of `chunk` slices through the device
+    each iteration.  Timed over `iters` iterations from zero, against the
+    device-resident iterates after the same number of steps, and against the
+    PCIe copy rates measured here."""
+    import torch
+
+    import synth
+    from paper_2304_12934_amd import MBIR, HostMBIR, Plan
+
+    plan_c = Plan.uniform_stack(n, n, synth.uniform_angles(na), chunk, device=dev)
+    b_host = b.cpu().reshape(-1).pin_memory()
+    m = HostMBIR(plan_c, b_host, nz // chunk, prior, L_data=L_data)
+    m.step()                                      # warm-up, then restart from zero
+    m.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.run(iters)
+    dt = time.perf_counter() - t0
+    ref = MBIR(plan, b, prior, L_data=L_data)
+    ref.run(iters)
+    torch.cuda.synchronize()
+    x_ref = ref.x.cpu()
+    diff = float(torch.linalg.vector_norm(m.x - x_ref) / torch.linalg.vector_norm(x_ref))
+    del ref, x_ref
+    # bytes over PCIe per iteration: x_k and x_{k-1} with their halo slices and
+    # the data in, x_{k+1} out
+    chunks = nz // chunk
+    slices_in = 2 * (nz + 2 * (chunks - 1))
+    gb_in = (slices_in * n * n + nz * na * n) * 4 / 1e9
+    gb_out = nz * n * n * 4 / 1e9
+    src = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32).pin_memory()
+    dst = torch.empty(src.numel(), dtype=torch.float32, device=dev)
+    rates = []
+    for a, c in ((src, dst), (dst, src)):
+        c.copy_(a, non_blocking=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            c.copy_(a, non_blocking=True)
+        torch.cuda.synchronize()
+        rates.append(3 * src.numel() * 4 / (time.perf_counter() - t) / 1e9)
+    bound = 1.0 / max(gb_in / rates[0], gb_out / rates[1])
+    out = {"chunk_slices": chunk, "chunks": chunks, "iterations": iters, "iters_per_s": round(iters / dt, 3),
+           "GB_in_per_iter": round(gb_in, 2), "GB_out_per_iter": round(gb_out, 2),
+           "h2d_GB_per_s": round(rates[0], 1), "d2h_GB_per_s": round(rates[1], 1),
+           "pcie_bound_iters_per_s": round(bound, 3), "rel_diff_vs_resident": float(f"{diff:.3g}"),
+           "restarts": m.restarts}
+    plan_c.close()
+    del m, b_host, src, dst
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out
