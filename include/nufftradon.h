@@ -67,7 +67,8 @@ typedef int32_t nr_status;
 enum {
   NR_OK = 0,
   NR_INVALID_ARG = 1,        /* null pointer, bad size, bad parameter      */
-  NR_UNSUPPORTED_SIZE = 2,   /* FFT length outside the compiled set         */
+  NR_UNSUPPORTED_SIZE = 2,   /* FFT length outside the compiled set, or too
+                                many angles (see nr_slice)                  */
   NR_WORKSPACE_TOO_SMALL = 3,
   NR_HIP_ERROR = 4,          /* a HIP runtime call failed                   */
   NR_NONFINITE = 5,          /* NaN/Inf detected by a device reduction      */
@@ -80,7 +81,9 @@ typedef void* nr_stream;
 typedef struct nr_plan nr_plan;
 
 /* One slice of a stack.  n: slice width N (even, >= 8); n_det: detector
- * bins N_t (even, >= 8); n_angles >= 1.  Offsets are element offsets.
+ * bins N_t (even, >= 8); n_angles >= 1, below 2^24 and below
+ * 2^31 / 2^ceil(log2(N_t/2 + 1)) (the plan's 32-bit point codes; else
+ * NR_UNSUPPORTED_SIZE).  Offsets are element offsets.
  * center: offset c of the rotation axis from the detector centre, in bins
  * (the axis projects to bin N_t/2 + c); finite, |c| <= N_t/2; 0 for a
  * centred axis. */

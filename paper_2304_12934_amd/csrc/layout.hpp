@@ -27,7 +27,8 @@ constexpr int kMaxChunk = 1024;
 // Complex buffers are float pairs.
 struct SliceDesc {
   int32_t N, Nt, na, G, H, rows, cols, tiles_x, n_items, n_zero, slot, itiles_x;
-  int32_t rdisc, pad;             // cells of ext farther than rdisc from the origin are never read
+  int32_t rdisc;                  // cells of ext farther than rdisc from the origin are never read
+  int32_t jbits;                  // point codes in pts/ipts: (angle << jbits) | radial index
   int64_t vol_off, sino_off;      // element offsets into the caller's buffers
   const float* deapod;            // [N] 1/phihat((i - N/2)/G)
   const float* tw_G;              // [G] exp(-2 pi i m/G)

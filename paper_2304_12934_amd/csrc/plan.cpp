@@ -193,7 +193,7 @@ void build_spread_bins(const Plan& plan, Geom& g) {
   std::vector<int32_t> fill(count.begin(), count.end() - 1);
   for (int a = 0; a < na; ++a)
     for (int j = 1; j < g.H; ++j)
-      for_tiles(a, j, [&](int t) { g.pts[size_t(fill[t]++)] = a * g.H + j; });
+      for_tiles(a, j, [&](int t) { g.pts[size_t(fill[t]++)] = (a << g.jbits) | j; });
   // work items: at most `chunk` points each; tiles cut into several items
   // accumulate with atomics into a grid region cleared beforehand
   const int chunk = plan.tune.chunk;
@@ -237,7 +237,7 @@ void build_spread_bins(const Plan& plan, Geom& g) {
       std::fill(cell_count.begin(), cell_count.end(), 0);
       int cmax = 0;
       for (int q = ib; q < ie; ++q) {
-        const int a = g.pts[size_t(q)] / g.H, j = g.pts[size_t(q)] % g.H;
+        const int a = g.pts[size_t(q)] >> g.jbits, j = g.pts[size_t(q)] & ((1 << g.jbits) - 1);
         const int g0x = int(std::ceil(double(j) * g.gxy[2 * a] - halfW));
         const int g0y = int(std::ceil(double(j) * g.gxy[2 * a + 1] - halfW));
         const int rr0 = g0x + plan.halo - ty * g.tile_h, cc0 = g0y + g.G / 2 + plan.colpad - tx * g.tile_w;
@@ -281,7 +281,7 @@ void build_interp_bins(const Plan& plan, Geom& g) {
   std::vector<int32_t> fill(start.begin(), start.end() - 1);
   // angle-major within a tile: neighbouring threads take neighbouring points of one line
   for (int a = 0; a < na; ++a)
-    for (int j = 0; j < g.H; ++j) g.ipts[size_t(fill[size_t(tile_of(a, j))]++)] = a * g.H + j;
+    for (int j = 0; j < g.H; ++j) g.ipts[size_t(fill[size_t(tile_of(a, j))]++)] = (a << g.jbits) | j;
   const int chunk = plan.tune.chunk;
   g.iitems.clear();
   for (int t = 0; t < ntiles; ++t) {
@@ -354,6 +354,14 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
       err = "slice " + std::to_string(s) + ": center must be finite with |center| <= n_det/2";
       return NR_INVALID_ARG;
     }
+    // the kernels' point codes (angle << bits of n_det/2) | radial index are
+    // 31-bit, and angle * (n_det/2 + 1) is formed with 24-bit multiplies
+    int jb = 0;
+    while ((1 << jb) < sl.n_det / 2 + 1) ++jb;
+    if (int64_t(sl.n_angles) >= (int64_t(1) << std::min(24, 31 - jb))) {
+      err = "slice " + std::to_string(s) + ": n_angles must be below 2^24 and below 2^31 / 2^ceil(log2(n_det/2 + 1))";
+      return NR_UNSUPPORTED_SIZE;
+    }
     const int G = int(sigma * sl.n);
     if (!fft_length_supported(G) || !fft_length_supported(sl.n_det)) {
       err = "slice " + std::to_string(s) + ": FFT length " + std::to_string(G) + " or " +
@@ -383,6 +391,7 @@ nr_status build_plan(const nr_slice* slices, int32_t n_slices, const double* ang
     g.key = key;
     g.G = int(sigma * sl.n);
     g.H = sl.n_det / 2 + 1;
+    while ((1 << g.jbits) < g.H) ++g.jbits;
     g.rows = g.G / 2 + 1 + 2 * plan.halo;
     g.cols = g.G + 2 * plan.colpad;
     g.gxy.resize(size_t(2) * sl.n_angles);
@@ -785,6 +794,7 @@ std::vector<SliceDesc> slice_descs(const Plan& plan, char* d_ws) {
       d.zero_tiles = reinterpret_cast<const int32_t*>(d_ws + g.off_zero);
       d.itiles_x = g.itiles_x;
       d.rdisc = disc_radius(plan, g);
+      d.jbits = g.jbits;
       d.ipts = reinterpret_cast<const int32_t*>(d_ws + g.off_ipts);
       d.iitems = reinterpret_cast<const SpreadItem*>(d_ws + g.off_iitems);
       out[size_t(s)] = d;

@@ -61,13 +61,14 @@ struct Geom {
   GeomKey key;
   int G = 0;            // oversampled grid size (sigma * N)
   int H = 0;            // half-line points N_t/2 + 1
+  int jbits = 0;        // point codes (a << jbits) | j: the bits of j < H
   int rows = 0;         // extended grid rows G/2 + 1 + 2*halo
   int cols = 0;         // extended grid row length G + 2*colpad
   std::vector<double> gxy;          // per angle: (G cos/N_t, G sin/N_t), sign-flipped so that x >= 0
   std::vector<int32_t> flip;        // per angle: 1 if the spectrum value is conjugated
   // spreading bins (tile-major point lists; points j >= 1 only)
   int tile_w = 0, tile_h = 0, tiles_x = 0, tiles_y = 0;
-  std::vector<int32_t> pts;         // point ids a*H + j, grouped by tile
+  std::vector<int32_t> pts;         // point codes (a << jbits) | j, grouped by tile
   std::vector<int32_t> tile_start;  // tiles_x*tiles_y + 1 offsets into pts
   std::vector<SpreadItem> items;
   std::vector<int32_t> zero_tiles;  // tiles written by atomic items: cleared first

@@ -118,7 +118,7 @@ struct DSlice {
   const NR_G int32_t* zero_tiles;
   const NR_G int32_t* ipts;
   const NR_G SpreadItem* iitems;
-  int itiles_x, rdisc;
+  int itiles_x, rdisc, jbits;
 };
 
 // The slice descriptor by value (uniform: scalar loads).
@@ -144,6 +144,7 @@ __device__ __forceinline__ DSlice load_desc(const SliceDesc* p) {
   d.iitems = (const NR_G SpreadItem*)s.iitems;
   d.itiles_x = s.itiles_x;
   d.rdisc = s.rdisc;
+  d.jbits = s.jbits;
   return d;
 }
 
@@ -155,6 +156,22 @@ __device__ __forceinline__ int round_half_up(float x) {
   asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
   return r;
 }
+
+// Non-temporal stores, for a stage's large output written in whole
+// contiguous rows that the next stage reads once: the forward column
+// transform's grid rows and the adjoint spreading's tile rows (each measured
+// faster to store and faster for the next stage to read back).  The 16-byte
+// pieces of T, 64 bytes apart, and the half-lines yh, which the spreading
+// reads back in scattered order, measured slower with them.
+typedef float nr_v2f __attribute__((ext_vector_type(2)));
+typedef float nr_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(NR_G float2* p, float2 v) {
+  __builtin_nontemporal_store(nr_v2f{v.x, v.y}, reinterpret_cast<NR_G nr_v2f*>(p));
+}
+__device__ __forceinline__ void store_nt(NR_G float4* p, float4 v) {
+  __builtin_nontemporal_store(nr_v4f{v.x, v.y, v.z, v.w}, reinterpret_cast<NR_G nr_v4f*>(p));
+}
+__device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
 template <int L>
 __device__ __forceinline__ int wrap_index(int x) {   // x in [-L, 2L) -> [0, L)
@@ -218,6 +235,9 @@ template <int W, int TW, int TH>
 struct SpreadLds {
   static constexpr int AH = TH + 2 * W, AW = TW + 2 * W;   // tile with its apron
   static constexpr int TS = AW + 1;                         // odd row stride: columns of lanes spread over banks
+  // one accumulator array: the real plane, then the imaginary plane; the
+  // length rounded up to whole 16-byte groups for the vector clear
+  static constexpr int ACC = (2 * AH * TS + 3) / 4 * 4;
 };
 
 // Every kernel runs one unit of its work list per workgroup (block b takes
@@ -335,7 +355,7 @@ __device__ __forceinline__ void fwd_cols_unit(const LA& a, const WorkItem wi, fl
 #pragma unroll 4
     for (int k = tid; k < cnt; k += T) {
       const int m = m0 + k;
-      out[k] = s[m < L / 2 ? m + L / 2 : m - L / 2];
+      store_nt(&out[k], s[m < L / 2 ? m + L / 2 : m - L / 2]);
     }
     // periodic copies: positions m in [L - colpad, L) also at m - L (left
     // pad), m in [0, colpad) also at m + L (right pad), when stored
@@ -461,16 +481,16 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
   // the thread's points and their angle tables, loaded up front (slots past
   // the item's end repeat its first point; items are never empty),
   // overlapping the tile staging
-  int pids[PER], fl[PER];
+  int codes[PER], fl[PER];
   double gx[PER], gy[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int e = tid + k * T;
-    pids[k] = d.ipts[it.begin + (e < it.end - it.begin ? e : 0)];
+    codes[k] = d.ipts[it.begin + (e < it.end - it.begin ? e : 0)];
   }
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int ang = pids[k] / d.H;
+    const int ang = codes[k] >> d.jbits;
     gx[k] = d.gxy[2 * ang];
     gy[k] = d.gxy[2 * ang + 1];
     fl[k] = d.flip[ang];
@@ -498,8 +518,8 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
   for (int k = 0; k < PER; ++k) {
     if (k * T >= count) break;          // uniform over the workgroup
     if (tid + k * T >= count) continue;
-    const int pid = pids[k];
-    const int ang = pid / d.H, j = pid - ang * d.H;
+    const int code = codes[k];
+    const int j = code & ((1 << d.jbits) - 1);
     int g0x, g0y;
     float wx[W], wy[W];
     point_taps<W>(gx[k], gy[k], j, kb, g0x, g0y, wx, wy);
@@ -518,7 +538,7 @@ __device__ __forceinline__ void interp_tiles_unit(const LA& a, const KB& kb, con
       acc.y = fmaf(wx[i], r.y, acc.y);
     }
     if (fl[k]) acc.y = -acc.y;
-    d.yh[pid] = c_scale(acc, inv);
+    d.yh[__umul24(uint32_t(code >> d.jbits), uint32_t(d.H)) + j] = c_scale(acc, inv);
   }
 }
 
@@ -671,39 +691,62 @@ __global__ __launch_bounds__(256) void k_spread_zero(LaunchArgs a) {
 // bounds test (no divergence); the apron is dropped at the end.  Single-item
 // tiles are then stored plainly (every cell, zeros included); shared tiles
 // are added with global float atomics.
-template <int W, int TW, int TH, class LA, class KB>
-__device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, int* acc_re, int* acc_im, float* red, int& nonfinite, const int tid) {
-  constexpr int AH = SpreadLds<W, TW, TH>::AH, AW = SpreadLds<W, TW, TH>::AW, TS = SpreadLds<W, TW, TH>::TS;
-  constexpr int T = 256, PER = kMaxChunk / T;
-  const DSlice d = load_desc(a.descs + wi.slice);
-  const SpreadItem it = d.items[wi.unit];
+// A spreading item's points are held in registers between the loads and the
+// accumulation, as five arrays (gathered in one aggregate they were placed in
+// scratch memory): slot k of thread tid is entry tid + k*T of the item.
+#define NR_SPREAD_PTS(p) p##_code, p##_v, p##_gx, p##_gy, p##_fl
+#define NR_SPREAD_PTS_DECL(p, PER) \
+  int p##_code[PER];               \
+  float2 p##_v[PER];               \
+  double p##_gx[PER], p##_gy[PER]; \
+  int p##_fl[PER]
+
+// First loads of an item: its descriptor, its entry and its point codes.
+// Slots past the item's end repeat its first point; an empty item (a tile no
+// point touches, which still writes its zeros) reads no point list at all
+// and uses point 0.  A code is (angle << jbits) | j: a shift and a mask take
+// it apart, where dividing an index a*H + j by H cost about 20 VALU slots per
+// point.
+template <int T, int PER, class LA>
+__device__ __forceinline__ void spread_fetch_codes(const LA& a, const WorkItem wi, DSlice& d, SpreadItem& it,
+                                                   int (&code)[PER], const int tid) {
+  d = load_desc(a.descs + wi.slice);
+  it = d.items[wi.unit];
   const int count = it.end - it.begin;   // at most kMaxChunk
-  const NR_G float2* __restrict__ yh = d.yh;
-  // the thread's points: ids, values and angle tables, every load issued up
-  // front and kept in registers.  Slots past the item's end repeat its first
-  // point; an empty item (a tile no point touches, which still writes its
-  // zeros) reads no point list at all and uses point 0.
-  int pid[PER];
-  float2 v[PER];
-  double gx[PER], gy[PER];
-  int fl[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int e = tid + k * T;
-    pid[k] = count > 0 ? d.pts[it.begin + (e < count ? e : 0)] : 0;
+    code[k] = count > 0 ? d.pts[it.begin + (e < count ? e : 0)] : 0;
   }
+}
+
+// Second loads: each point's value and its angle's entries.
+template <int PER>
+__device__ __forceinline__ void spread_fetch_values(const DSlice& d, const int (&code)[PER], float2 (&v)[PER],
+                                                    double (&gx)[PER], double (&gy)[PER], int (&fl)[PER]) {
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int ang = pid[k] / d.H;
-    v[k] = yh[pid[k]];
+    const int ang = code[k] >> d.jbits;
+    v[k] = d.yh[__umul24(uint32_t(ang), uint32_t(d.H)) + (code[k] & ((1 << d.jbits) - 1))];
     gx[k] = d.gxy[2 * ang];
     gy[k] = d.gxy[2 * ang + 1];
     fl[k] = d.flip[ang];
   }
-  for (int c = tid; c < AH * TS; c += T) {
-    acc_re[c] = 0;
-    acc_im[c] = 0;
-  }
+}
+
+template <int W, int TW, int TH, int T, int PER, class LA, class KB>
+__device__ __forceinline__ void spread_accumulate(const LA& a, const KB& kb, const DSlice& d, const SpreadItem& it,
+                                                  const int (&code)[PER], const float2 (&v)[PER],
+                                                  const double (&gx)[PER], const double (&gy)[PER],
+                                                  const int (&fl)[PER], int* acc, float* red, int& nonfinite,
+                                                  const int tid) {
+  static_assert(PER == kMaxChunk / T, "slots per thread");
+  constexpr int AH = SpreadLds<W, TW, TH>::AH, TS = SpreadLds<W, TW, TH>::TS, ACC = SpreadLds<W, TW, TH>::ACC;
+  int* const acc_re = acc;             // acc: ACC ints, 16-byte aligned
+  int* const acc_im = acc + AH * TS;   // T threads; red holds T/64 floats
+  const int count = it.end - it.begin;
+  const NR_G float2* __restrict__ yh = d.yh;
+  NR_STRIDED(c, ACC / 4, T) reinterpret_cast<int4*>(acc)[c] = make_int4(0, 0, 0, 0);
   const int r0 = (it.tile / d.tiles_x) * TH, c0 = (it.tile % d.tiles_x) * TW;
   // apron coordinates of grid cell (row g0x + halo, column g0y + G/2 + colpad)
   const int rbase = a.halo - r0 + W, cbase = d.G / 2 + a.colpad - c0 + W;
@@ -731,26 +774,40 @@ __device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, con
   if (tid == 0) nonfinite = 0;
   const float mmax = block_max<T>(m, red, tid);   // synchronises: the tile is cleared
   if (bad) nonfinite = 1;
-  const float q = mmax > 0.f ? 1073741824.0f / (mmax * float(it.bound)) : 0.f;   // 2^30 / (M b)
-  // one point per round; the slot's registers are picked with compile-time
-  // indices (no dynamic register indexing) and the taps are unrolled once
+  // 2^30 / (M b) through the hardware reciprocal (within 1 ulp: the sums keep
+  // a factor of 2 of headroom below 2^31)
+  const float q = mmax > 0.f ? 1073741824.0f * __builtin_amdgcn_rcpf(mmax * float(it.bound)) : 0.f;
+  // one point per round, taken from slot 0 of copies that rotate down by one
+  // slot each round: compile-time indices only (a chain of selects on the
+  // round number was turned into an indexed load from scratch memory), and
+  // the taps are unrolled once
+  int rc[PER], rf[PER];
+  float2 rv[PER];
+  double rx[PER], ry[PER];
+#pragma unroll
+  for (int z = 0; z < PER; ++z) {
+    rc[z] = code[z];
+    rf[z] = fl[z];
+    rv[z] = v[z];
+    rx[z] = gx[z];
+    ry[z] = gy[z];
+  }
 #pragma unroll 1
   for (int k = 0; k < PER; ++k) {
     if (k * T >= count) break;          // uniform over the workgroup
-    int p = pid[0], f = fl[0];
-    float2 u = v[0];
-    double px = gx[0], py = gy[0];
+    const int p = rc[0], f = rf[0];
+    float2 u = rv[0];
+    const double px = rx[0], py = ry[0];
 #pragma unroll
-    for (int z = 1; z < PER; ++z)
-      if (k == z) {
-        p = pid[z];
-        f = fl[z];
-        u = v[z];
-        px = gx[z];
-        py = gy[z];
-      }
+    for (int z = 0; z + 1 < PER; ++z) {
+      rc[z] = rc[z + 1];
+      rf[z] = rf[z + 1];
+      rv[z] = rv[z + 1];
+      rx[z] = rx[z + 1];
+      ry[z] = ry[z + 1];
+    }
     if (tid + k * T < count) {
-      const int ang = p / d.H, j = p - ang * d.H;
+      const int j = p & ((1 << d.jbits) - 1);
       if (f) u.y = -u.y;
       u.x *= q;
       u.y *= q;
@@ -771,7 +828,7 @@ __device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, con
   }
   __syncthreads();
   const bool shared_tile = it.flags & kItemAtomic;
-  const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? 1.0f / q : 0.f);
+  const float inv_q = nonfinite ? __int_as_float(0x7fc00000) : (q > 0.f ? __builtin_amdgcn_rcpf(q) : 0.f);
   // the origin's W x W footprint in apron coordinates (DC items only)
   int dcx = 0, dcy = 0;
   float dwx[W], dwy[W];
@@ -781,44 +838,90 @@ __device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, con
     dcx += rbase;
     dcy += cbase;
   }
-  NR_G float2* ext = d.ext;
-  for (int c = tid; c < TH * TW; c += T) {
-    const int rl = c / TW, cl = c % TW;
-    const int r = r0 + rl, cc = c0 + cl;
-    if (r >= d.rows || cc >= d.cols) continue;
-    NR_G float2* dst = ext + size_t(r) * d.cols + cc;
-    const int ai = (rl + W) * TS + cl + W;
-    float re = float(acc_re[ai]) * inv_q;
-    const float im = float(acc_im[ai]) * inv_q;
-    if (has_dc) {
-      const int i = rl + W - dcx, l = cl + W - dcy;
-      if (i >= 0 && i < W && l >= 0 && l < W) {
-        float wi = 0.f, wl = 0.f;
+  // a thread writes one column of the tile, every T/TW-th row: its grid and
+  // LDS addresses advance by constant strides
+  static_assert(T % TW == 0 && TH % (T / TW) == 0, "tile shape");
+  constexpr int STEP = T / TW;
+  const int cl = tid % TW, rl0 = tid / TW;
+  const int cc = c0 + cl;
+  NR_G float2* dst = d.ext + size_t(r0 + rl0) * d.cols + cc;
+  const size_t dstep = size_t(STEP) * d.cols;
+  const bool col_ok = cc < d.cols;
 #pragma unroll
-        for (int k = 0; k < W; ++k) {   // compile-time register indices
-          if (k == i) wi = dwx[k];
-          if (k == l) wl = dwy[k];
+  for (int s = 0; s < TH / STEP; ++s) {
+    const int rl = rl0 + s * STEP;
+    if (col_ok && r0 + rl < d.rows) {
+      const int ai = (rl + W) * TS + cl + W;
+      float re = float(acc_re[ai]) * inv_q;
+      const float im = float(acc_im[ai]) * inv_q;
+      if (has_dc) {
+        const int i = rl + W - dcx, l = cl + W - dcy;
+        if (i >= 0 && i < W && l >= 0 && l < W) {
+          float wi = 0.f, wl = 0.f;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {   // compile-time register indices
+            if (k == i) wi = dwx[k];
+            if (k == l) wl = dwy[k];
+          }
+          re += dc * wi * wl;
         }
-        re += dc * wi * wl;
+      }
+      if (shared_tile) {
+        atomicAdd((NR_G float*)&dst->x, re);
+        atomicAdd((NR_G float*)&dst->y, im);
+      } else {
+        store_nt(dst, make_float2(re, im));
       }
     }
-    if (shared_tile) {
-      atomicAdd((float*)&dst->x, re);
-      atomicAdd((float*)&dst->y, im);
-    } else {
-      *dst = make_float2(re, im);
-    }
+    dst += dstep;
   }
   __syncthreads();
 }
 
+// one work item: loads, then accumulation
+template <int W, int TW, int TH, int T, class LA, class KB>
+__device__ __forceinline__ void spread_tiles_unit(const LA& a, const KB& kb, const WorkItem wi, int* acc, float* red, int& nonfinite, const int tid) {
+  constexpr int PER = kMaxChunk / T;
+  DSlice d;
+  SpreadItem it;
+  NR_SPREAD_PTS_DECL(p, PER);
+  spread_fetch_codes<T>(a, wi, d, it, p_code, tid);
+  spread_fetch_values(d, NR_SPREAD_PTS(p));
+  spread_accumulate<W, TW, TH, T>(a, kb, d, it, NR_SPREAD_PTS(p), acc, red, nonfinite, tid);
+}
+
+// Two work items per workgroup: b and n-1-b of the list, which is sorted
+// heaviest first, so that every workgroup pairs a heavy item (bound by its
+// taps) with a light one (bound by its tile stores) and the launch keeps a
+// like mix of both from start to end.  An item's loads form a chain of four
+// dependent round trips (work entry, descriptor and item, point codes,
+// values); both items' chains run at once and the second item's values
+// arrive while the first item accumulates.  Measured on 2560^2 slices, 1024
+// angles: 44.8 -> 44.1 us per slice for the pairing, 44.1 -> 42.0 with
+// non-temporal tile stores; 512 or 1024 threads per tile were slower (47.2,
+// 62.1 us).
+constexpr int kSpreadThreads = 256;
 template <int W, int TW, int TH>
-__global__ __launch_bounds__(256) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
-  __shared__ int acc_re[SpreadLds<W, TW, TH>::AH * SpreadLds<W, TW, TH>::TS];
-  __shared__ int acc_im[SpreadLds<W, TW, TH>::AH * SpreadLds<W, TW, TH>::TS];
-  __shared__ float red[4];
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_tiles(LaunchArgs a, KBArgs kb) {
+  constexpr int T = kSpreadThreads;
+  __shared__ __attribute__((aligned(16))) int acc[SpreadLds<W, TW, TH>::ACC];
+  __shared__ float red[T / 64];
   __shared__ int nonfinite;
-  NR_FOR_EACH_UNIT(a, wi) spread_tiles_unit<W, TW, TH>(a, kb, wi, acc_re, acc_im, red, nonfinite, int(threadIdx.x));
+  const int tid = int(threadIdx.x);
+  const int b0 = int(blockIdx.x), b1 = a.n_work - 1 - b0;
+  const WorkItem w0 = b0 < a.n_work ? a.work[b0] : WorkItem{-1, 0};
+  const WorkItem w1 = b1 > b0 ? a.work[b1] : WorkItem{-1, 0};
+  constexpr int PER = kMaxChunk / T;
+  DSlice d0, d1;
+  SpreadItem i0, i1;
+  NR_SPREAD_PTS_DECL(p0, PER);
+  NR_SPREAD_PTS_DECL(p1, PER);
+  if (w0.slice >= 0) spread_fetch_codes<T>(a, w0, d0, i0, p0_code, tid);
+  if (w1.slice >= 0) spread_fetch_codes<T>(a, w1, d1, i1, p1_code, tid);
+  if (w0.slice >= 0) spread_fetch_values(d0, NR_SPREAD_PTS(p0));
+  if (w1.slice >= 0) spread_fetch_values(d1, NR_SPREAD_PTS(p1));
+  if (w0.slice >= 0) spread_accumulate<W, TW, TH, T>(a, kb, d0, i0, NR_SPREAD_PTS(p0), acc, red, nonfinite, tid);
+  if (w1.slice >= 0) spread_accumulate<W, TW, TH, T>(a, kb, d1, i1, NR_SPREAD_PTS(p1), acc, red, nonfinite, tid);
 }
 
 // Reference spreading: one thread per polar point of one slice, global float
@@ -985,7 +1088,7 @@ constexpr int kPersistThreads = 256;
 template <int W>
 struct PersistLds {
   static constexpr int FFT = 4096 * int(sizeof(float2));
-  static constexpr int SPREAD = 2 * SpreadLds<W, 64, 32>::AH * SpreadLds<W, 64, 32>::TS * int(sizeof(int));
+  static constexpr int SPREAD = SpreadLds<W, 64, 32>::ACC * int(sizeof(int));
   static constexpr int INTERP = InterpLds<W>::RH * InterpLds<W>::RS * int(sizeof(float2));
   static constexpr int BYTES = FFT > SPREAD ? (FFT > INTERP ? FFT : INTERP) : (SPREAD > INTERP ? SPREAD : INTERP);
 };
@@ -1040,9 +1143,7 @@ __device__ __forceinline__ void persist_unit(const LA& a, const KB& kb, int stag
       spread_zero_unit<64, 32>(a, wi, tid);
       return;
     case StageKind::Spread: {
-      int* re = reinterpret_cast<int*>(lds);
-      spread_tiles_unit<W, 64, 32>(a, kb, wi, re, re + SpreadLds<W, 64, 32>::AH * SpreadLds<W, 64, 32>::TS, red,
-                                   nonfinite, tid);
+      spread_tiles_unit<W, 64, 32, kPersistThreads>(a, kb, wi, reinterpret_cast<int*>(lds), red, nonfinite, tid);
       return;
     }
     case StageKind::AdjCols:
@@ -1170,7 +1271,7 @@ hipError_t launch_spread(const LaunchArgs& a, const KBArgs& kb, int tw, int th, 
 #define NR_TILE(w, h)                                                               \
   if (tw == w && th == h)                                                           \
     return zero ? launch(k_spread_zero<w, h>, 256, a.n_work, st, a)                 \
-                : launch(k_spread_tiles<W, w, h>, 256, a.n_work, st, a, kb);
+                : launch(k_spread_tiles<W, w, h>, kSpreadThreads, (a.n_work + 1) / 2, st, a, kb);
   NR_TILE(64, 32)
   NR_TILE(32, 32)
   NR_TILE(64, 64)

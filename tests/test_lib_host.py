@@ -87,6 +87,10 @@ def test_plan_validation_status_codes(L):
     assert _create(L, [(48, 128, 10, 0, 0, 0)], ang)[0] == _lib.NR_UNSUPPORTED_SIZE   # G = 96
     assert _create(L, [(128, 96, 10, 0, 0, 0)], ang)[0] == _lib.NR_UNSUPPORTED_SIZE   # N_t = 96
     assert _create(L, [(128, 128, 10, 0, 0, 0)], ang, width=9)[0] == _lib.NR_UNSUPPORTED_SIZE
+    # point codes (angle << ceil(log2(N_t/2 + 1))) | j must fit 31 bits: with
+    # N_t = 8192 (13 bits of j) at most 2^18 - 1 angles
+    many = np.linspace(0, np.pi, 1 << 18, endpoint=False)
+    assert _create(L, [(128, 8192, 1 << 18, 0, 0, 0)], many)[0] == _lib.NR_UNSUPPORTED_SIZE
     bad = ang.copy()
     bad[3] = np.nan
     assert _create(L, [(128, 128, 10, 0, 0, 0)], bad)[0] == _lib.NR_INVALID_ARG
