@@ -330,6 +330,7 @@ nr_status run_batches(nr_plan* plan, bool fwd, const float* b, bool adj, const f
         nrk::LaunchArgs la = a;
         la.work = reinterpret_cast<const WorkItem*>(base + p.off_work + sl.work_off);
         la.n_work = sl.n_work;
+        la.stream_stores = bt.bytes > nr::kLastLevelCacheBytes ? 1 : 0;
         // the stage that writes the sinogram rows subtracts b as it stores them
         if (sl.stage == nr::Stage::FwdRadial || (sl.stage == nr::Stage::FwdInterp && sl.L > 0)) la.sino_sub = b;
         e = timed(plan, stage_event_id(sl.stage), bs, [&] {

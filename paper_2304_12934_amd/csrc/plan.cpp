@@ -548,6 +548,7 @@ nr_status layout_plan(Plan& plan, std::string& err) {
       used += need;
     }
     b0 += int(bt.slices.size());
+    bt.bytes = used;
     plan.slot_area = std::max(plan.slot_area, used);
     plan.n_slots = std::max(plan.n_slots, int(bt.slices.size()));
     // FFT lengths present in this batch

@@ -111,8 +111,15 @@ struct StageLaunch {
   int n_work;         // entries (XCD padding included)
 };
 
+// The MI355X's last-level cache (Infinity Cache), 256 MiB.  A batch whose
+// scratch grids exceed it has its stages store their large row outputs with
+// non-temporal stores (the next stage finds them in HBM either way); a batch
+// that fits keeps plain stores, so that the next stage reads from the cache.
+constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
+
 struct Batch {
   int lane = 0;                   // stream (and scratch area) the batch runs on
+  size_t bytes = 0;               // scratch bytes of its slices (T, ext, yh)
   std::vector<int> slices;
   std::vector<size_t> slot_off;   // scratch offset of each slice inside its lane's slot area
   std::vector<StageLaunch> fwd, adj;

@@ -160,9 +160,11 @@ __device__ __forceinline__ int round_half_up(float x) {
 // Non-temporal stores, for a stage's large output written in whole
 // contiguous rows that the next stage reads once: the forward column
 // transform's grid rows and the adjoint spreading's tile rows (each measured
-// faster to store and faster for the next stage to read back).  The 16-byte
-// pieces of T, 64 bytes apart, and the half-lines yh, which the spreading
-// reads back in scattered order, measured slower with them.
+// faster to store and faster for the next stage to read back, when the
+// batch's grids exceed the last-level cache; the launch's stream_stores
+// says so).  The 16-byte pieces of T, 64 bytes apart, and the half-lines yh,
+// which the spreading reads back in scattered order, measured slower with
+// them; grids that fit in the last-level cache, slower too.
 typedef float nr_v2f __attribute__((ext_vector_type(2)));
 typedef float nr_v4f __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_nt(NR_G float2* p, float2 v) {
@@ -355,7 +357,11 @@ __device__ __forceinline__ void fwd_cols_unit(const LA& a, const WorkItem wi, fl
 #pragma unroll 4
     for (int k = tid; k < cnt; k += T) {
       const int m = m0 + k;
-      store_nt(&out[k], s[m < L / 2 ? m + L / 2 : m - L / 2]);
+      const float2 v = s[m < L / 2 ? m + L / 2 : m - L / 2];
+      if (a.stream_stores)
+        store_nt(&out[k], v);
+      else
+        out[k] = v;
     }
     // periodic copies: positions m in [L - colpad, L) also at m - L (left
     // pad), m in [0, colpad) also at m + L (right pad), when stored
@@ -870,7 +876,10 @@ __device__ __forceinline__ void spread_accumulate(const LA& a, const KB& kb, con
         atomicAdd((NR_G float*)&dst->x, re);
         atomicAdd((NR_G float*)&dst->y, im);
       } else {
-        store_nt(dst, make_float2(re, im));
+        if (a.stream_stores)
+          store_nt(dst, make_float2(re, im));
+        else
+          *dst = make_float2(re, im);
       }
     }
     dst += dstep;

@@ -21,6 +21,7 @@ struct LaunchArgs {
   int fbp_filter;           // adjoint radial weight: -1 none, 0 ramp, 1 ramp x Butterworth
   int fbp_order;
   float fbp_inv_cutoff;
+  int stream_stores;        // 1: the forward columns and the spreading store their rows non-temporally
 };
 
 // Arguments of a persistent launch (one batch): the per-XCD queues of
