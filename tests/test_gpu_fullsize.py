@@ -159,3 +159,30 @@ def test_largest_transform_lengths_sampled(n, nd, na, sample):
     e = rel(g, ora.radon_adj(y[sample], ang[sample], n))
     print(f"adj rel L2: {e:.3e}", flush=True)
     assert e < TOL
+
+
+def test_batch_above_last_level_cache(setup):
+    """Two 2560^2 slices in one batch (about 282 MB of grids, above the 256 MiB
+    last-level cache, so the forward column transform and the spreading store
+    their rows with non-temporal stores) against the same slices in one-slice
+    batches (plain stores), and the batched forward against the oracle on
+    sampled angles."""
+    from paper_2304_12934_amd import Plan
+    dev, ang, f, _ = setup
+    print("case: 2 x 2560^2 in one batch vs one-slice batches", flush=True)
+    f2 = np.stack([f, synth.ellipse_phantom(2, 3, N, 20).numpy()])
+    x = torch.as_tensor(f2, dtype=torch.float32, device=dev)
+    big = Plan.uniform_stack(N, N, ang, 2, device=dev, tuning={"batch_mb": 400})
+    small = Plan.uniform_stack(N, N, ang, 2, device=dev, tuning={"batch_mb": 160})
+    assert big.info()["batches"] == 1 and small.info()["batches"] == 2
+    sb, gb = (t.cpu().numpy() for t in big.normal(x))
+    ss, gs = (t.cpu().numpy() for t in small.normal(x))
+    big.close()
+    small.close()
+    e_s, e_g = rel(sb, ss), rel(gb, gs)
+    print(f"one batch vs two: fwd {e_s:.3e}, normal {e_g:.3e}", flush=True)
+    # the same kernels and sums; only split tiles add in a different order
+    assert e_s < 1e-6 and e_g < 1e-6
+    e = rel(sb[1][SAMPLE], ora.radon_fwd(f2[1], ang[SAMPLE], N))
+    print(f"batched fwd rel L2 on {len(SAMPLE)} angles: {e:.3e}", flush=True)
+    assert e < TOL
