@@ -242,8 +242,10 @@ struct SpreadLds {
   static constexpr int ACC = (2 * AH * TS + 3) / 4 * 4;
 };
 
-// Every kernel runs one unit of its work list per workgroup (block b takes
-// entry b); padding entries (slice < 0) and blocks past the list do nothing.
+// The transform kernels run one unit of their work list per workgroup (block
+// b takes entry b; the forward columns, the interpolation and the spreading
+// take two, see there); padding entries (slice < 0) and blocks past the list
+// do nothing.
 #define NR_FOR_EACH_UNIT(a, wi)                                                                    \
   if (const WorkItem wi = int(blockIdx.x) < (a).n_work ? (a).work[blockIdx.x] : WorkItem{-1, 0}; \
       wi.slice >= 0)
@@ -376,7 +378,24 @@ __device__ __forceinline__ void fwd_cols_unit(const LA& a, const WorkItem wi, fl
 template <int L>
 __global__ __launch_bounds__(fft_threads(L)) void k_fwd_cols(LaunchArgs a) {
   __shared__ float2 sbuf[lds_elems<L>()];
-  NR_FOR_EACH_UNIT(a, wi) fwd_cols_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
+  // Launches of many columns (a.pair_units) take two per workgroup:
+  // positions p and p + 8 of the XCD-interleaved list (both on this
+  // workgroup's XCD), as two calls with a barrier between (a loop over the
+  // two kept values live across them and doubled the VGPRs).  Measured on
+  // 2560^2 slices in launches of 8: 40.0 -> 37.2 us per slice; launches of
+  // one 1280^2 or 2048^2 slice (1281 or 2049 columns) ran slower with half
+  // as many workgroups, and the same pairing made the row transforms and
+  // the adjoint columns slower (21.7 -> 22.3, 24.4 -> 28.6, 34.0 -> 43.4 us).
+  if (a.pair_units) {
+    const int p0 = 16 * (int(blockIdx.x) >> 3) + (int(blockIdx.x) & 7), p1 = p0 + 8;
+    const WorkItem w0 = p0 < a.n_work ? a.work[p0] : WorkItem{-1, 0};
+    const WorkItem w1 = p1 < a.n_work ? a.work[p1] : WorkItem{-1, 0};
+    if (w0.slice >= 0) fwd_cols_unit<L, fft_threads(L)>(a, w0, sbuf, int(threadIdx.x));
+    __syncthreads();
+    if (w1.slice >= 0) fwd_cols_unit<L, fft_threads(L)>(a, w1, sbuf, int(threadIdx.x));
+  } else {
+    NR_FOR_EACH_UNIT(a, wi) fwd_cols_unit<L, fft_threads(L)>(a, wi, sbuf, int(threadIdx.x));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,6 +1389,10 @@ hipError_t launch_spread(const LaunchArgs& a, const KBArgs& kb, int tw, int th, 
   return hipErrorInvalidValue;
 }
 
+// forward column launches with at least this many columns run two per
+// workgroup (at least about ten rounds of resident workgroups either way)
+constexpr int kPairColumnsMin = 8192;
+
 hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArgs& kb, int W, int tile_w,
                         int tile_h, hipStream_t st) {
   if (a.n_work <= 0) return hipSuccess;
@@ -1381,13 +1404,17 @@ hipError_t launch_stage(StageKind stage, int L, const LaunchArgs& a, const KBArg
 #undef NR_CASE
       }
       break;
-    case StageKind::FwdCols:
+    case StageKind::FwdCols: {
+      LaunchArgs b = a;
+      b.pair_units = a.n_work >= kPairColumnsMin ? 1 : 0;
+      const int grid = b.pair_units ? (a.n_work + 15) / 16 * 8 : a.n_work;
       switch (L) {
-#define NR_CASE(l) case l: return launch(k_fwd_cols<l>, fft_threads(l), a.n_work, st, a);
+#define NR_CASE(l) case l: return launch(k_fwd_cols<l>, fft_threads(l), grid, st, b);
         NR_LENGTHS(NR_CASE)
 #undef NR_CASE
       }
       break;
+    }
     case StageKind::FwdInterp:
       if (L == 0) {   // tiled interpolation (the radial pass is its own stage)
         if (W == 6) return launch(k_interp_tiles<6>, 256, (a.n_work + 1) / 2, st, a, kb);

@@ -22,6 +22,7 @@ struct LaunchArgs {
   int fbp_order;
   float fbp_inv_cutoff;
   int stream_stores;        // 1: the forward columns and the spreading store their rows non-temporally
+  int pair_units;           // set by launch_stage: 1 when the forward columns run two units per workgroup
 };
 
 // Arguments of a persistent launch (one batch): the per-XCD queues of
